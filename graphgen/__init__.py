@@ -1,0 +1,190 @@
+"""Seeded synthetic inputs: directed graphs in CSR form plus per-edge probabilities.
+
+This module is shared by the HIP path's tests/benchmarks and by the CPU oracle's
+tests.  It holds only input generation (graph topology and the edge-probability
+scheme handed to the library as float32); none of the influence-maximisation
+arithmetic (hashing, thresholds, sketches, estimates) lives here.
+
+Graph families stand in for the paper's social networks (Table 2), which are not
+available here: Erdos-Renyi, R-MAT (power-law, like the SNAP social graphs) and
+Barabasi-Albert (undirected, stored as two arcs per edge as the paper does for
+its undirected graphs).  Probability schemes follow Section 2.1: uniform IC,
+weighted cascade (w_uv = 1/indeg(v)) and the trivalency mix.
+"""
+from __future__ import annotations
+
+import dataclasses
+import os
+from typing import Optional
+
+import numpy as np
+
+__all__ = [
+    "Graph", "csr_from_edges", "erdos_renyi", "rmat", "barabasi_albert",
+    "uniform_p", "weighted_cascade_p", "trivalency_p", "with_p",
+    "save_npz", "load_npz", "cached",
+]
+
+
+@dataclasses.dataclass
+class Graph:
+    """CSR by source: out-edges of u are col[rowptr[u]:rowptr[u+1]], sorted ascending,
+    no duplicates, no self-loops.  p[e] is the float32 IC probability of edge e."""
+    n: int
+    rowptr: np.ndarray          # int64[n+1]
+    col: np.ndarray             # int32[m]
+    p: Optional[np.ndarray]     # float32[m]
+    name: str = ""
+
+    @property
+    def m(self) -> int:
+        return int(self.col.shape[0])
+
+    def src(self) -> np.ndarray:
+        """Source vertex of every edge (int32[m])."""
+        return np.repeat(np.arange(self.n, dtype=np.int32), np.diff(self.rowptr))
+
+    def out_degree(self) -> np.ndarray:
+        return np.diff(self.rowptr)
+
+    def in_degree(self) -> np.ndarray:
+        return np.bincount(self.col, minlength=self.n).astype(np.int64)
+
+
+def csr_from_edges(n: int, src: np.ndarray, dst: np.ndarray) -> Graph:
+    """Build a CSR graph: self-loops dropped, duplicate arcs merged to one arc."""
+    src = np.asarray(src, dtype=np.int64)
+    dst = np.asarray(dst, dtype=np.int64)
+    keep = src != dst
+    key = np.unique(src[keep] * np.int64(n) + dst[keep])
+    s = key // n
+    d = (key % n).astype(np.int32)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(s, minlength=n), out=rowptr[1:])
+    return Graph(n=n, rowptr=rowptr, col=np.ascontiguousarray(d), p=None)
+
+
+def erdos_renyi(n: int, m: int, seed: int = 1) -> Graph:
+    """m distinct directed arcs with uniform endpoints; self-loops and repeats redrawn."""
+    if m > n * (n - 1):
+        raise ValueError("too many edges for a simple digraph")
+    rng = np.random.Generator(np.random.PCG64(seed))
+    keys = np.empty(0, dtype=np.int64)
+    order = np.empty(0, dtype=np.int64)
+    while keys.size < m:
+        need = m - keys.size
+        s = rng.integers(0, n, size=need, dtype=np.int64)
+        d = rng.integers(0, n, size=need, dtype=np.int64)
+        k = s * n + d
+        k = k[s != d]
+        allk = np.concatenate([keys, k])
+        # keep first occurrence in draw order so the result is independent of batch size
+        _, first = np.unique(allk, return_index=True)
+        first.sort()
+        keys = allk[first][:m]
+    g = csr_from_edges(n, keys // n, keys % n)
+    g.name = f"er_n{n}_m{m}_s{seed}"
+    return g
+
+
+def rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19,
+         c: float = 0.19, seed: int = 1, relabel: bool = True,
+         chunk: int = 1 << 24) -> Graph:
+    """R-MAT: edge_factor * 2^scale recursive-quadrant draws, then dedup and
+    self-loop removal.  With relabel, vertex ids get a seeded random permutation
+    so hubs are scattered over the id space."""
+    n = 1 << scale
+    m_draw = edge_factor << scale
+    rng = np.random.Generator(np.random.PCG64(seed))
+    keys = []
+    ab, abc = a + b, a + b + c
+    left = m_draw
+    while left > 0:
+        cnt = min(chunk, left)
+        left -= cnt
+        s = np.zeros(cnt, dtype=np.int64)
+        d = np.zeros(cnt, dtype=np.int64)
+        for lvl in range(scale):
+            r = rng.random(cnt)
+            sbit = r >= ab
+            dbit = ((r >= a) & (r < ab)) | (r >= abc)
+            s |= sbit.astype(np.int64) << lvl
+            d |= dbit.astype(np.int64) << lvl
+        keys.append(s * n + d)
+    k = np.concatenate(keys)
+    s, d = k // n, k % n
+    if relabel:
+        perm = rng.permutation(n).astype(np.int64)
+        s, d = perm[s], perm[d]
+    g = csr_from_edges(n, s, d)
+    g.name = f"rmat{scale}_ef{edge_factor}_s{seed}"
+    return g
+
+
+def barabasi_albert(n: int, m0: int = 8, seed: int = 0) -> Graph:
+    """Undirected preferential-attachment graph, two arcs per edge."""
+    import networkx as nx
+    gx = nx.barabasi_albert_graph(n, m0, seed=seed)
+    e = np.asarray(gx.edges(), dtype=np.int64).reshape(-1, 2)
+    src = np.concatenate([e[:, 0], e[:, 1]])
+    dst = np.concatenate([e[:, 1], e[:, 0]])
+    g = csr_from_edges(n, src, dst)
+    g.name = f"ba_n{n}_m{m0}_s{seed}"
+    return g
+
+
+# ---------------------------------------------------------------- probability schemes
+
+def uniform_p(g: Graph, p: float) -> np.ndarray:
+    return np.full(g.m, p, dtype=np.float32)
+
+
+def weighted_cascade_p(g: Graph) -> np.ndarray:
+    """Weighted cascade: every in-arc of v gets 1/indeg(v) (indeg of the final,
+    deduplicated, loop-free graph), rounded to float32."""
+    indeg = g.in_degree()
+    return (1.0 / indeg[g.col].astype(np.float64)).astype(np.float32)
+
+
+def trivalency_p(g: Graph, seed: int = 2) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    choices = np.array([0.1, 0.01, 0.001], dtype=np.float32)
+    return choices[rng.integers(0, 3, size=g.m)]
+
+
+def with_p(g: Graph, scheme: str, seed: int = 2) -> Graph:
+    """Return a shallow copy of g carrying the named probability scheme:
+    'wc', 'trivalency', or a float literal such as '0.01'."""
+    if scheme == "wc":
+        p = weighted_cascade_p(g)
+    elif scheme == "trivalency":
+        p = trivalency_p(g, seed)
+    else:
+        p = uniform_p(g, float(scheme))
+    return Graph(n=g.n, rowptr=g.rowptr, col=g.col, p=p, name=f"{g.name}_{scheme}")
+
+
+# ---------------------------------------------------------------- caching
+
+def save_npz(g: Graph, path: str) -> None:
+    np.savez(path, n=np.int64(g.n), rowptr=g.rowptr, col=g.col,
+             p=(g.p if g.p is not None else np.empty(0, np.float32)),
+             name=np.array(g.name))
+
+
+def load_npz(path: str) -> Graph:
+    z = np.load(path, allow_pickle=False)
+    p = z["p"]
+    return Graph(n=int(z["n"]), rowptr=z["rowptr"], col=z["col"],
+                 p=(p if p.size else None), name=str(z["name"]))
+
+
+def cached(path: Optional[str], make) -> Graph:
+    """Load a graph from `path` if present, else build it with make() and store it."""
+    if path and os.path.exists(path):
+        return load_npz(path)
+    g = make()
+    if path:
+        os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+        save_npz(g, path)
+    return g
