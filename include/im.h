@@ -1,0 +1,149 @@
+/*
+ * im.h -- C ABI of the MI355X sketch-based influence-maximisation library
+ * (libimx.so).  The method is DiFuseR's (Gokturk and Kaya): Monte-Carlo
+ * independent-cascade simulations whose live edges are decided by hashing
+ * (Section 2.2, Eq. 1-2), one count-distinct register per (vertex,
+ * simulation) (Section 2.3, Eq. 3-5; Section 3.1), pull-based register
+ * propagation (Section 3.2, Alg. 2), harmonic-mean cardinality estimates
+ * (Section 3.1, Eq. 7), greedy selection with a union-frontier covering
+ * cascade (Section 3.3, Alg. 3) and the error-adaptive rebuild test
+ * (Section 4, Alg. 4).  All computation runs in HIP kernels on one gfx950 GPU.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named *_host are host memory owned by the caller; the library
+ *     copies inputs and writes outputs, and keeps no reference after return.
+ *   - Handles are owned by the library until the matching *_free call.  A graph
+ *     must outlive every sketch built on it.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     device work of a handle is ordered on the stream it was created with;
+ *     functions that return host results synchronise that stream.
+ *   - Errors: a status code is returned and a message is kept per thread
+ *     (im_last_error).  Nothing throws across the ABI.  A failed call leaves
+ *     existing handles unchanged; *out is left NULL.
+ *   - One thread at a time per handle; distinct handles are independent.
+ */
+#ifndef IMX_IM_H
+#define IMX_IM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum im_status {
+    IM_OK = 0,
+    IM_EINVAL = 1,  /* malformed argument (CSR, probability, J, K ...)        */
+    IM_ENOMEM = 2,  /* device memory (or an admission budget) too small       */
+    IM_EDEVICE = 3, /* HIP runtime error or no gfx950 device                  */
+    IM_ESTATE = 4   /* call not allowed in the handle's current state         */
+} im_status;
+
+typedef struct im_graph im_graph;
+typedef struct im_sketch im_sketch;
+
+/* Counters of one sketch.  Times are device time measured with HIP events on
+ * the sketch's stream. */
+typedef struct im_stats {
+    int32_t build_sweeps;    /* propagation sweeps of the initial build, including
+                                the final sweep that changed nothing            */
+    int32_t rebuilds;        /* rebuilds triggered by the error-adaptive test   */
+    int64_t total_sweeps;    /* sweeps over the initial build and all rebuilds  */
+    int64_t cascade_levels;  /* union-frontier levels over all cascades         */
+    double build_ms;         /* im_sketch_build: fill + propagation + estimate  */
+    double select_ms;        /* im_select_seeds, end to end                     */
+    double propagate_ms;     /* propagation sweeps only (build and rebuilds)    */
+    double cascade_ms;       /* covering cascades only                          */
+} im_stats;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* im_last_error(void);
+
+/* Library version (major, minor). */
+im_status im_version(int32_t* major, int32_t* minor);
+
+/*
+ * Load a directed graph G=(V,E) with IC edge probabilities w (Section 2.1;
+ * problem input of Alg. 4).
+ *   n       number of vertices, 1 <= n < 2^31.
+ *   m       number of arcs, 0 <= m < 2^40.
+ *   rowptr_host  int64[n+1], CSR by source: out-arcs of u are
+ *           col_host[rowptr[u] .. rowptr[u+1]).  rowptr[0]=0, non-decreasing,
+ *           rowptr[n]=m.
+ *   col_host     int32[m] destination ids in [0,n), strictly increasing within
+ *           each row (parallel arcs must be merged by the caller into one arc
+ *           with the compound probability, as Section 2.1 describes).
+ *   p_host       float32[m] probability of each arc in [0,1] (no NaN).  It is
+ *           turned on the device into the 31-bit fixed-point threshold
+ *           W = min(2^31, floor(p * 2^31)) used by the live test of Eq. 2.
+ *   stream  stream for the upload and all later work on the graph.
+ *   out     receives the handle.
+ * Errors: IM_EINVAL for any violation above (message names the first bad
+ * index), IM_ENOMEM if the device cannot hold the graph, IM_EDEVICE.
+ */
+im_status im_graph_load(int64_t n, int64_t m, const int64_t* rowptr_host, const int32_t* col_host,
+                        const float* p_host, void* stream, im_graph** out);
+
+/* Number of vertices and arcs of a loaded graph. */
+im_status im_graph_info(const im_graph* g, int64_t* n, int64_t* m);
+
+void im_graph_free(im_graph* g);
+
+/*
+ * Build the sketches of all vertices (Alg. 4 before its greedy loop):
+ * J simulations with random values X drawn from `seed` and sorted
+ * (Section 4.1), registers filled with each vertex's own rank (Alg. 1,
+ * Eq. 3) and propagated backwards along live arcs until no register
+ * changes (Alg. 2, Eq. 5).  Then per-vertex estimate terms are computed.
+ *   J     registers (= simulations) per vertex: a multiple of 64 in [64, 4096].
+ *   seed  64-bit seed of the simulation values and of the register hashes.
+ * The register array takes n*J bytes of device memory, vertex-major with each
+ * row's registers in increasing simulation order (Section 3.1).
+ * Errors: IM_EINVAL (bad J, NULL graph), IM_ENOMEM, IM_EDEVICE.
+ */
+im_status im_sketch_build(const im_graph* g, int32_t J, uint64_t seed, void* stream, im_sketch** out);
+
+/*
+ * Greedy selection of K seeds (Alg. 4 loop): per pick, harmonic-mean
+ * estimates (Eq. 7) -> argmax over non-seeds (exact rational compare of
+ * J_u^2/H_u, lowest id on ties) -> covering cascade from the pick (Alg. 3) ->
+ * score T (covered (vertex, simulation) pairs) -> if the pick is not the
+ * last and 100*(T - T_old) > T, refill uncovered registers and propagate
+ * again, then T_old = T.
+ *   K          1 <= K <= n.
+ *   seeds_host int32[K] output, in pick order.
+ *   spread_out optional double: T_K / J, the expected spread of the seed set
+ *              over the J simulations.
+ *   est_host   optional double[K]: estimated marginal gain of each pick,
+ *              alpha_J * 2^33 * J_s^2 / (J * H_s) (0 when J_s = 0).
+ *   T_host     optional uint64[K]: T after each pick's cascade.
+ *   stats_out  optional counters and device times.
+ * The sketch is consumed: a second call returns IM_ESTATE.
+ * Errors: IM_EINVAL (K out of range, NULL seeds), IM_ESTATE, IM_EDEVICE.
+ */
+im_status im_select_seeds(im_sketch* s, int32_t K, int32_t* seeds_host, double* spread_out, double* est_host,
+                          uint64_t* T_host, im_stats* stats_out);
+
+/* Copy the current registers to host memory uint8[n*J] (vertex-major; covered
+ * registers read 0, uncovered ones hold rank values 1..33).  Parity hook. */
+im_status im_sketch_registers(const im_sketch* s, uint8_t* regs_host);
+
+/* Copy the current per-vertex estimate terms: Ju_host uint32[n] = number of
+ * uncovered registers, Hu_host uint64[n] = sum over them of 2^(33 - M).  Either
+ * pointer may be NULL.  Parity hook. */
+im_status im_sketch_estimates(const im_sketch* s, uint32_t* Ju_host, uint64_t* Hu_host);
+
+/* Counters of the sketch so far. */
+im_status im_sketch_stats(const im_sketch* s, im_stats* out);
+
+/* Sorted simulation values X (uint32[J], 31-bit) of the sketch.  Parity hook. */
+im_status im_sketch_sim_values(const im_sketch* s, uint32_t* X_host);
+
+void im_sketch_free(im_sketch* s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IMX_IM_H */

@@ -1,0 +1,227 @@
+"""Thin ctypes binding of libimx.so (include/im.h).  Argument marshalling only:
+every step of the method runs in the library's HIP kernels.
+
+Function names mirror the C ABI (im_graph_load, im_sketch_build,
+im_select_seeds, ...).  `stream` arguments take a hipStream_t as an int (for
+example torch.cuda.current_stream().cuda_stream) or None for the null stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libimx.so")
+
+IM_OK, IM_EINVAL, IM_ENOMEM, IM_EDEVICE, IM_ESTATE = range(5)
+_STATUS = {1: "IM_EINVAL", 2: "IM_ENOMEM", 3: "IM_EDEVICE", 4: "IM_ESTATE"}
+
+
+class IMError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class im_stats(ctypes.Structure):
+    _fields_ = [
+        ("build_sweeps", ctypes.c_int32),
+        ("rebuilds", ctypes.c_int32),
+        ("total_sweeps", ctypes.c_int64),
+        ("cascade_levels", ctypes.c_int64),
+        ("build_ms", ctypes.c_double),
+        ("select_ms", ctypes.c_double),
+        ("propagate_ms", ctypes.c_double),
+        ("cascade_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+# Every symbol declared in include/im.h.
+EXPORTS = [
+    "im_last_error", "im_version", "im_graph_load", "im_graph_info", "im_graph_free",
+    "im_sketch_build", "im_select_seeds", "im_sketch_registers", "im_sketch_estimates",
+    "im_sketch_stats", "im_sketch_sim_values", "im_sketch_free",
+]
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libimx.so.  Raises if the HIP library has not been built: there is no
+    fallback implementation."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"HIP library missing: {LIB_PATH} (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+        L.im_last_error.argtypes = []
+        L.im_last_error.restype = ctypes.c_char_p
+        L.im_version.argtypes = [P, P]
+        L.im_graph_load.argtypes = [i64, i64, P, P, P, P, P]
+        L.im_graph_info.argtypes = [P, P, P]
+        L.im_graph_free.argtypes = [P]
+        L.im_graph_free.restype = None
+        L.im_sketch_build.argtypes = [P, i32, u64, P, P]
+        L.im_select_seeds.argtypes = [P, i32, P, P, P, P, P]
+        L.im_sketch_registers.argtypes = [P, P]
+        L.im_sketch_estimates.argtypes = [P, P, P]
+        L.im_sketch_stats.argtypes = [P, P]
+        L.im_sketch_sim_values.argtypes = [P, P]
+        L.im_sketch_free.argtypes = [P]
+        L.im_sketch_free.restype = None
+        for name in EXPORTS:
+            if name not in ("im_last_error", "im_graph_free", "im_sketch_free"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st: int) -> None:
+    if st != IM_OK:
+        raise IMError(st, lib().im_last_error().decode(errors="replace"))
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return int(stream.cuda_stream)
+    return int(stream)
+
+
+# ---------------------------------------------------------------- C-named wrappers
+
+def im_graph_load(n: int, rowptr: np.ndarray, col: np.ndarray, p: np.ndarray, stream=None) -> ctypes.c_void_p:
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    p = np.ascontiguousarray(p, dtype=np.float32)
+    if rowptr.shape[0] != n + 1:
+        raise IMError(IM_EINVAL, "rowptr must have n+1 entries")
+    m = int(col.shape[0])
+    if p.shape[0] != m:
+        raise IMError(IM_EINVAL, "p must have m entries")
+    out = ctypes.c_void_p()
+    _check(lib().im_graph_load(n, m, _p(rowptr), _p(col), _p(p), _stream(stream), ctypes.byref(out)))
+    return out
+
+
+def im_graph_free(g) -> None:
+    lib().im_graph_free(g)
+
+
+def im_sketch_build(g, J: int, seed: int, stream=None) -> ctypes.c_void_p:
+    out = ctypes.c_void_p()
+    _check(lib().im_sketch_build(g, J, seed & (2**64 - 1), _stream(stream), ctypes.byref(out)))
+    return out
+
+
+def im_select_seeds(s, K: int):
+    seeds = np.zeros(K, dtype=np.int32)
+    est = np.zeros(K, dtype=np.float64)
+    T = np.zeros(K, dtype=np.uint64)
+    spread = ctypes.c_double()
+    stats = im_stats()
+    _check(lib().im_select_seeds(s, K, _p(seeds), ctypes.byref(spread), _p(est), _p(T), ctypes.byref(stats)))
+    return dict(seeds=seeds, spread=spread.value, est=est, T=T, stats=stats.as_dict())
+
+
+def im_sketch_registers(s, n: int, J: int) -> np.ndarray:
+    M = np.zeros((n, J), dtype=np.uint8)
+    _check(lib().im_sketch_registers(s, _p(M)))
+    return M
+
+
+def im_sketch_estimates(s, n: int):
+    Ju = np.zeros(n, dtype=np.uint32)
+    Hu = np.zeros(n, dtype=np.uint64)
+    _check(lib().im_sketch_estimates(s, _p(Ju), _p(Hu)))
+    return Ju, Hu
+
+
+def im_sketch_stats(s) -> dict:
+    st = im_stats()
+    _check(lib().im_sketch_stats(s, ctypes.byref(st)))
+    return st.as_dict()
+
+
+def im_sketch_sim_values(s, J: int) -> np.ndarray:
+    X = np.zeros(J, dtype=np.uint32)
+    _check(lib().im_sketch_sim_values(s, _p(X)))
+    return X
+
+
+def im_sketch_free(s) -> None:
+    lib().im_sketch_free(s)
+
+
+# ---------------------------------------------------------------- convenience handles
+
+class Graph:
+    """Device-resident graph (owns an im_graph handle)."""
+
+    def __init__(self, n: int, rowptr, col, p, stream=None):
+        self.n = int(n)
+        self.m = int(len(col))
+        self.handle = im_graph_load(self.n, rowptr, col, p, stream)
+
+    @classmethod
+    def from_graphgen(cls, g, stream=None) -> "Graph":
+        return cls(g.n, g.rowptr, g.col, g.p, stream)
+
+    def free(self) -> None:
+        if self.handle:
+            im_graph_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Sketch:
+    """Sketches of a graph (owns an im_sketch handle)."""
+
+    def __init__(self, graph: Graph, J: int, seed: int, stream=None):
+        self.graph = graph
+        self.J = int(J)
+        self.seed = int(seed)
+        self.handle = im_sketch_build(graph.handle, self.J, self.seed, stream)
+
+    def select(self, K: int) -> dict:
+        return im_select_seeds(self.handle, K)
+
+    def registers(self) -> np.ndarray:
+        return im_sketch_registers(self.handle, self.graph.n, self.J)
+
+    def estimates(self):
+        return im_sketch_estimates(self.handle, self.graph.n)
+
+    def sim_values(self) -> np.ndarray:
+        return im_sketch_sim_values(self.handle, self.J)
+
+    def stats(self) -> dict:
+        return im_sketch_stats(self.handle)
+
+    def free(self) -> None:
+        if self.handle:
+            im_sketch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

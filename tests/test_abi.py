@@ -1,0 +1,81 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared
+symbol, and rejects malformed input with IM_EINVAL before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "im.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(im_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree(imx):
+    assert _declared_symbols() == sorted(imx.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(imx):
+    L = ctypes.CDLL(imx.binding.LIB_PATH)
+    for name in _declared_symbols():
+        assert hasattr(L, name), name
+
+
+def test_version(imx):
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    assert imx.lib().im_version(ctypes.byref(a), ctypes.byref(b)) == 0
+    assert (a.value, b.value) >= (0, 1)
+
+
+def _load(imx, n, rowptr, col, p):
+    return imx.im_graph_load(n, np.asarray(rowptr, np.int64), np.asarray(col, np.int32), np.asarray(p, np.float32))
+
+
+@pytest.mark.parametrize("n,rowptr,col,p,msg", [
+    (3, [1, 1, 2, 2], [1, 2], [0.1, 0.1], "rowptr[0]"),
+    (3, [0, 2, 1, 2], [1, 2], [0.1, 0.1], "decreases"),
+    (3, [0, 1, 1, 1], [1, 2], [0.1, 0.1], "rowptr[n]"),
+    (3, [0, 1, 2, 2], [1, 3], [0.1, 0.1], "out of range"),
+    (3, [0, 1, 2, 2], [1, -1], [0.1, 0.1], "out of range"),
+    (3, [0, 2, 2, 2], [2, 1], [0.1, 0.1], "strictly increasing"),
+    (3, [0, 2, 2, 2], [1, 1], [0.1, 0.1], "strictly increasing"),
+    (3, [0, 1, 2, 2], [1, 2], [0.1, float("nan")], "p outside"),
+    (3, [0, 1, 2, 2], [1, 2], [1.5, 0.1], "p outside"),
+    (3, [0, 1, 2, 2], [1, 2], [0.1, -0.01], "p outside"),
+])
+def test_graph_load_rejects_malformed_csr(imx, n, rowptr, col, p, msg):
+    with pytest.raises(imx.IMError) as ei:
+        _load(imx, n, rowptr, col, p)
+    assert ei.value.status == 1 and msg in str(ei.value)
+
+
+def test_graph_load_rejects_empty_vertex_set(imx):
+    out = ctypes.c_void_p()
+    assert imx.lib().im_graph_load(0, 0, None, None, None, None, ctypes.byref(out)) == 1
+    assert out.value is None
+
+
+def test_null_handles_are_rejected(imx):
+    L = imx.lib()
+    out = ctypes.c_void_p()
+    assert L.im_sketch_build(None, 64, 1, None, ctypes.byref(out)) == 1
+    assert L.im_select_seeds(None, 1, None, None, None, None, None) == 1
+    assert L.im_sketch_registers(None, None) == 1
+    assert L.im_graph_info(None, None, None) == 1
+    L.im_graph_free(None)
+    L.im_sketch_free(None)
+
+
+def test_no_silent_cpu_fallback(imx):
+    """Without a GPU the library fails loudly instead of computing on the host."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(imx.IMError) as ei:
+        _load(imx, 3, [0, 1, 2, 2], [1, 2], [0.5, 0.5])
+    assert ei.value.status == 3

@@ -1,0 +1,200 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Everything the method computes is integer, so the bar is bit-exact: simulation
+values, registers after the build, estimate terms (J_u, H_u), seeds, covered
+counts T per pick, final registers; the reported estimates are one IEEE double
+expression of exact integers and must match to the last bit as well.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_gpu(imx, g, J, seed, K):
+    G = imx.Graph.from_graphgen(g)
+    S = imx.Sketch(G, J, seed)
+    out = dict(X=S.sim_values(), M0=S.registers())
+    out["Ju0"], out["Hu0"] = S.estimates()
+    out.update(S.select(K))
+    out["Mf"] = S.registers()
+    out["Juf"], out["Huf"] = S.estimates()
+    S.free()
+    G.free()
+    return out
+
+
+def assert_parity(orc, gpu, ref, J, seed):
+    assert np.array_equal(gpu["X"], orc.sim_values(seed, J)), "simulation values"
+    assert np.array_equal(gpu["M0"], ref["M_build0"]), "registers after build"
+    assert np.array_equal(gpu["Ju0"], ref["Ju0"]), "J_u after build"
+    assert np.array_equal(gpu["Hu0"], ref["Hu0"]), "H_u after build"
+    assert list(gpu["seeds"]) == list(ref["seeds"]), "seeds"
+    assert list(gpu["T"]) == list(ref["T"]), "T per pick"
+    assert gpu["est"].tobytes() == ref["est"].tobytes(), "estimates"
+    assert gpu["spread"] == ref["spread"]
+    assert np.array_equal(gpu["Mf"], ref["M_final"]), "final registers"
+    Ju, Hu = orc.estimates(gpu["Mf"])
+    assert np.array_equal(gpu["Juf"], Ju) and np.array_equal(gpu["Huf"], Hu), "final estimate terms"
+    rebuilds = int(np.count_nonzero(ref["sweeps"][1:]))
+    assert gpu["stats"]["rebuilds"] == rebuilds
+
+
+def _hub_graph():
+    # one hub with 1500 out-arcs (split into several propagation tasks) plus
+    # random arcs; ragged row lengths everywhere.
+    rng = np.random.default_rng(9)
+    n = 2000
+    src = np.concatenate([np.zeros(1500, np.int64), rng.integers(0, n, 6000)])
+    dst = np.concatenate([rng.permutation(np.arange(1, n))[:1500], rng.integers(0, n, 6000)])
+    return graphgen.with_p(graphgen.csr_from_edges(n, src, dst), "0.2")
+
+
+def _cycle(n):
+    return graphgen.with_p(graphgen.csr_from_edges(n, np.arange(n), (np.arange(n) + 1) % n), "1.0")
+
+
+CASES = {
+    "c1_er1k_p0.1_J64_s1": (lambda: graphgen.with_p(graphgen.erdos_renyi(1000, 5000, 1), "0.1"), 64, 1, 10),
+    "c1_er1k_p0.1_J64_s2": (lambda: graphgen.with_p(graphgen.erdos_renyi(1000, 5000, 1), "0.1"), 64, 2, 10),
+    "c1_er1k_p0.1_J64_s3": (lambda: graphgen.with_p(graphgen.erdos_renyi(1000, 5000, 1), "0.1"), 64, 3, 10),
+    "er400_wc_J128": (lambda: graphgen.with_p(graphgen.erdos_renyi(400, 4000, 2), "wc"), 128, 5, 8),
+    "er300_tri_J192": (lambda: graphgen.with_p(graphgen.erdos_renyi(300, 2000, 3), "trivalency"), 192, 6, 6),
+    "er500_p0.5_J320": (lambda: graphgen.with_p(graphgen.erdos_renyi(500, 3000, 4), "0.5"), 320, 7, 5),
+    "er200_p0.01_J1024": (lambda: graphgen.with_p(graphgen.erdos_renyi(200, 1200, 5), "0.01"), 1024, 8, 5),
+    "er150_p0.3_J4096": (lambda: graphgen.with_p(graphgen.erdos_renyi(150, 800, 6), "0.3"), 4096, 9, 3),
+    "hub2000_p0.2_J256": (_hub_graph, 256, 10, 5),
+    "rmat12_wc_J512": (lambda: graphgen.with_p(graphgen.rmat(12, 16, seed=3), "wc"), 512, 11, 5),
+    "ba3000_wc_J256": (lambda: graphgen.with_p(graphgen.barabasi_albert(3000, 8, seed=1), "wc"), 256, 12, 5),
+    "er100_p0_J64": (lambda: graphgen.with_p(graphgen.erdos_renyi(100, 500, 7), "0"), 64, 13, 4),
+    "cycle50_p1_J64": (lambda: _cycle(50), 64, 14, 5),
+    "er60_p1_J128_Kn": (lambda: graphgen.with_p(graphgen.erdos_renyi(60, 150, 8), "1.0"), 128, 15, 60),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_parity_with_oracle(imx, orc, name):
+    make, J, seed, K = CASES[name]
+    g = make()
+    _say(f"[parity] {name}: n={g.n} m={g.m} J={J} K={K} seed={seed}")
+    ref = orc.greedy(g, J, seed, K)
+    gpu = run_gpu(imx, g, J, seed, K)
+    assert_parity(orc, gpu, ref, J, seed)
+
+
+@pytest.mark.parametrize("n,K", [(1, 1), (10, 10)])
+def test_edgeless_graphs(imx, orc, n, K):
+    g = graphgen.Graph(n=n, rowptr=np.zeros(n + 1, np.int64), col=np.zeros(0, np.int32),
+                       p=np.zeros(0, np.float32))
+    _say(f"[edgeless] n={n} K={K}")
+    ref = orc.greedy(g, 64, 1, K)
+    gpu = run_gpu(imx, g, 64, 1, K)
+    assert_parity(orc, gpu, ref, 64, 1)
+
+
+def test_cycle_tie_break(imx):
+    gpu = run_gpu(imx, _cycle(30), 64, 3, 4)
+    assert list(gpu["seeds"]) == [0, 1, 2, 3]
+    assert list(gpu["T"]) == [30 * 64] * 4
+
+
+def test_schedule_independence_of_split(imx, orc, monkeypatch):
+    """Splitting hub rows into different numbers of tasks changes the schedule
+    of the in-place sweeps but not the fixed point or any output."""
+    g = _hub_graph()
+    outs = []
+    for split in ("64", "4096"):
+        monkeypatch.setenv("IMX_SPLIT", split)
+        _say(f"[schedule] split={split}")
+        outs.append(run_gpu(imx, g, 256, 21, 4))
+    a, b = outs
+    for key in ("M0", "Mf", "Ju0", "Hu0", "seeds", "T"):
+        assert np.array_equal(a[key], b[key]), key
+
+
+def test_repeat_builds_identical(imx):
+    g = graphgen.with_p(graphgen.rmat(11, 16, seed=5), "0.1")
+    a = run_gpu(imx, g, 512, 2, 6)
+    b = run_gpu(imx, g, 512, 2, 6)
+    for key in ("M0", "Mf", "seeds", "T", "est"):
+        assert np.array_equal(a[key], b[key]), key
+
+
+def test_select_twice_is_state_error(imx):
+    g = graphgen.with_p(graphgen.erdos_renyi(50, 200, 1), "0.1")
+    G = imx.Graph.from_graphgen(g)
+    S = imx.Sketch(G, 64, 1)
+    S.select(2)
+    with pytest.raises(imx.IMError) as ei:
+        S.select(2)
+    assert ei.value.status == 4
+    with pytest.raises(imx.IMError) as ei:
+        imx.Sketch(G, 100, 1)
+    assert ei.value.status == 1
+    S2 = imx.Sketch(G, 64, 1)
+    with pytest.raises(imx.IMError):
+        S2.select(51)
+
+
+# ---------------------------------------------------------------- full-size workload, sampled checks
+
+_C2 = {}
+
+
+def _c2_graph():
+    if "g" not in _C2:
+        _C2["g"] = graphgen.with_p(graphgen.rmat(20, 16, seed=1), "wc")
+    return _C2["g"]
+
+
+def test_rmat20_wc_full_size_sampled(imx, orc):
+    """RMAT scale 20, weighted cascade, J=512, K=50 -- the benchmark workload --
+    checked on outputs the oracle computes one at a time: sampled registers
+    against closed-form reachability, all estimate terms from the downloaded
+    registers, the first pick, and the final covered sets of sampled
+    simulations against BFS from the seed set."""
+    g = _c2_graph()
+    J, seed, K = 512, 1, 50
+    _say(f"[c2] n={g.n} m={g.m}")
+    G = imx.Graph.from_graphgen(g)
+    S = imx.Sketch(G, J, seed)
+    X = S.sim_values()
+    assert np.array_equal(X, orc.sim_values(seed, J))
+    M0 = S.registers()
+    Ju0, Hu0 = S.estimates()
+    r = S.select(K)
+    Mf = S.registers()
+    S.free()
+    G.free()
+
+    lg = orc.LiveGraph(g)
+    rng = np.random.default_rng(0)
+    deg = g.out_degree()
+    hubs = np.argsort(deg)[-20:]
+    us = np.concatenate([rng.integers(0, g.n, 150), hubs])
+    js = rng.integers(0, J, us.size)
+    for u, j in zip(us, js):
+        assert M0[u, j] == lg.reach_max(int(X[j]), seed, int(j), int(u)), (u, j)
+
+    Ju, Hu = orc.estimates(M0)
+    assert np.array_equal(Ju0, Ju) and np.array_equal(Hu0, Hu)
+    s0 = orc.argmax(Ju, Hu)
+    assert r["seeds"][0] == s0
+    assert r["est"][0] == orc.estimate_value(J, int(Ju[s0]), int(Hu[s0]))
+    assert len(set(r["seeds"].tolist())) == K
+
+    zeros = Mf == 0
+    assert int(zeros.sum()) == int(r["T"][-1])
+    assert r["spread"] == int(r["T"][-1]) / J
+    for j in rng.integers(0, J, 6):
+        cov = lg.cover_from(int(X[j]), r["seeds"])
+        assert np.array_equal(zeros[:, j], cov.astype(bool)), j
