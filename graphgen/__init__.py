@@ -70,7 +70,6 @@ def erdos_renyi(n: int, m: int, seed: int = 1) -> Graph:
         raise ValueError("too many edges for a simple digraph")
     rng = np.random.Generator(np.random.PCG64(seed))
     keys = np.empty(0, dtype=np.int64)
-    order = np.empty(0, dtype=np.int64)
     while keys.size < m:
         need = m - keys.size
         s = rng.integers(0, n, size=need, dtype=np.int64)
@@ -87,34 +86,39 @@ def erdos_renyi(n: int, m: int, seed: int = 1) -> Graph:
     return g
 
 
+def _rmat_chunk(child, cnt, scale, a, b, c):
+    rng = np.random.Generator(np.random.PCG64(child))
+    s = np.zeros(cnt, dtype=np.int64)
+    d = np.zeros(cnt, dtype=np.int64)
+    ab, abc = a + b, a + b + c
+    for lvl in range(scale):
+        r = rng.random(cnt)
+        s |= (r >= ab).astype(np.int64) << lvl
+        d |= (((r >= a) & (r < ab)) | (r >= abc)).astype(np.int64) << lvl
+    return s, d
+
+
 def rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19,
          c: float = 0.19, seed: int = 1, relabel: bool = True,
-         chunk: int = 1 << 24) -> Graph:
+         chunk: int = 1 << 22, threads: Optional[int] = None) -> Graph:
     """R-MAT: edge_factor * 2^scale recursive-quadrant draws, then dedup and
-    self-loop removal.  With relabel, vertex ids get a seeded random permutation
-    so hubs are scattered over the id space."""
+    self-loop removal.  Draws come in chunks with independent child seeds of
+    `seed`, so the graph does not depend on the thread count.  With relabel,
+    vertex ids get a seeded random permutation so hubs are scattered."""
+    from concurrent.futures import ThreadPoolExecutor
     n = 1 << scale
     m_draw = edge_factor << scale
-    rng = np.random.Generator(np.random.PCG64(seed))
-    keys = []
-    ab, abc = a + b, a + b + c
-    left = m_draw
-    while left > 0:
-        cnt = min(chunk, left)
-        left -= cnt
-        s = np.zeros(cnt, dtype=np.int64)
-        d = np.zeros(cnt, dtype=np.int64)
-        for lvl in range(scale):
-            r = rng.random(cnt)
-            sbit = r >= ab
-            dbit = ((r >= a) & (r < ab)) | (r >= abc)
-            s |= sbit.astype(np.int64) << lvl
-            d |= dbit.astype(np.int64) << lvl
-        keys.append(s * n + d)
-    k = np.concatenate(keys)
-    s, d = k // n, k % n
+    nchunks = (m_draw + chunk - 1) // chunk
+    children = np.random.SeedSequence(seed).spawn(nchunks + 1)
+    sizes = [min(chunk, m_draw - i * chunk) for i in range(nchunks)]
+    workers = threads or min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        parts = list(ex.map(lambda i: _rmat_chunk(children[i], sizes[i], scale, a, b, c), range(nchunks)))
+    s = np.concatenate([p[0] for p in parts])
+    d = np.concatenate([p[1] for p in parts])
+    del parts
     if relabel:
-        perm = rng.permutation(n).astype(np.int64)
+        perm = np.random.Generator(np.random.PCG64(children[-1])).permutation(n).astype(np.int64)
         s, d = perm[s], perm[d]
     g = csr_from_edges(n, s, d)
     g.name = f"rmat{scale}_ef{edge_factor}_s{seed}"
