@@ -53,8 +53,21 @@ typedef struct im_stats {
     int64_t cascade_levels;  /* union-frontier levels over all cascades         */
     double build_ms;         /* im_sketch_build: fill + propagation + estimate  */
     double select_ms;        /* im_select_seeds, end to end                     */
-    double propagate_ms;     /* propagation sweeps only (build and rebuilds)    */
+    double propagate_ms;     /* propagation phases (build and rebuilds), from the
+                                first sweep's start to the last sweep's end      */
     double cascade_ms;       /* covering cascades only                          */
+    int64_t prop_launches;   /* propagation kernel launches (= total_sweeps)    */
+    double prop_kernel_ms;   /* sum of per-launch propagation kernel times      */
+    /* Algorithmic traffic of the propagation kernel, counted by its
+     * instrumented variant when profiling level 2 is on (else all 0):
+     *   bytes = 28*tasks + 4*arcs_scanned + 4*arcs_active + 64*sectors
+     *         + J*rows_read + bytes_written + (n/4)*prop_launches
+     * (task record + row bounds; head ids; thresholds of arcs whose head
+     * changed; 64-byte sectors of head rows holding live registers; own rows
+     * read; changed register words stored; frontier bitmaps read and cleared). */
+    double prop_alg_bytes;
+    int64_t prop_tasks, prop_rows_read, prop_bytes_written;
+    int64_t prop_arcs_scanned, prop_arcs_active, prop_sectors;
 } im_stats;
 
 /* Message of the last failed call on this thread ("" if none). */
@@ -62,6 +75,16 @@ const char* im_last_error(void);
 
 /* Library version (major, minor). */
 im_status im_version(int32_t* major, int32_t* minor);
+
+/*
+ * Process-wide measurement switch for sketches built afterwards:
+ *   0  per-launch propagation kernel times only (HIP events; the default),
+ *   2  additionally run the instrumented propagation kernel, which counts the
+ *      algorithmic traffic reported in im_stats (slower; for roofline reports,
+ *      never for timing).
+ * Results are identical at every level.  Errors: IM_EINVAL for other levels.
+ */
+im_status im_set_profiling(int32_t level);
 
 /*
  * Load a directed graph G=(V,E) with IC edge probabilities w (Section 2.1;
@@ -128,6 +151,12 @@ im_status im_select_seeds(im_sketch* s, int32_t K, int32_t* seeds_host, double* 
 /* Copy the current registers to host memory uint8[n*J] (vertex-major; covered
  * registers read 0, uncovered ones hold rank values 1..33).  Parity hook. */
 im_status im_sketch_registers(const im_sketch* s, uint8_t* regs_host);
+
+/* Copy selected register rows to host memory: rows_host int32[nrows] vertex ids
+ * in [0, n), regs_host uint8[nrows*J] receives the rows in that order.  Parity
+ * hook for sketches too large to download whole.  Errors: IM_EINVAL for a bad
+ * id or NULL pointer. */
+im_status im_sketch_register_rows(const im_sketch* s, const int32_t* rows_host, int32_t nrows, uint8_t* regs_host);
 
 /* Copy the current per-vertex estimate terms: Ju_host uint32[n] = number of
  * uncovered registers, Hu_host uint64[n] = sum over them of 2^(33 - M).  Either

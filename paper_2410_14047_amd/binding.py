@@ -36,6 +36,15 @@ class im_stats(ctypes.Structure):
         ("select_ms", ctypes.c_double),
         ("propagate_ms", ctypes.c_double),
         ("cascade_ms", ctypes.c_double),
+        ("prop_launches", ctypes.c_int64),
+        ("prop_kernel_ms", ctypes.c_double),
+        ("prop_alg_bytes", ctypes.c_double),
+        ("prop_tasks", ctypes.c_int64),
+        ("prop_rows_read", ctypes.c_int64),
+        ("prop_bytes_written", ctypes.c_int64),
+        ("prop_arcs_scanned", ctypes.c_int64),
+        ("prop_arcs_active", ctypes.c_int64),
+        ("prop_sectors", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -44,8 +53,8 @@ class im_stats(ctypes.Structure):
 
 # Every symbol declared in include/im.h.
 EXPORTS = [
-    "im_last_error", "im_version", "im_graph_load", "im_graph_info", "im_graph_free",
-    "im_sketch_build", "im_select_seeds", "im_sketch_registers", "im_sketch_estimates",
+    "im_last_error", "im_version", "im_set_profiling", "im_graph_load", "im_graph_info", "im_graph_free",
+    "im_sketch_build", "im_select_seeds", "im_sketch_registers", "im_sketch_register_rows", "im_sketch_estimates",
     "im_sketch_stats", "im_sketch_sim_values", "im_sketch_free",
 ]
 
@@ -64,6 +73,7 @@ def lib() -> ctypes.CDLL:
         L.im_last_error.argtypes = []
         L.im_last_error.restype = ctypes.c_char_p
         L.im_version.argtypes = [P, P]
+        L.im_set_profiling.argtypes = [i32]
         L.im_graph_load.argtypes = [i64, i64, P, P, P, P, P]
         L.im_graph_info.argtypes = [P, P, P]
         L.im_graph_free.argtypes = [P]
@@ -71,6 +81,7 @@ def lib() -> ctypes.CDLL:
         L.im_sketch_build.argtypes = [P, i32, u64, P, P]
         L.im_select_seeds.argtypes = [P, i32, P, P, P, P, P]
         L.im_sketch_registers.argtypes = [P, P]
+        L.im_sketch_register_rows.argtypes = [P, P, i32, P]
         L.im_sketch_estimates.argtypes = [P, P, P]
         L.im_sketch_stats.argtypes = [P, P]
         L.im_sketch_sim_values.argtypes = [P, P]
@@ -116,6 +127,10 @@ def im_graph_load(n: int, rowptr: np.ndarray, col: np.ndarray, p: np.ndarray, st
     return out
 
 
+def im_set_profiling(level: int) -> None:
+    _check(lib().im_set_profiling(level))
+
+
 def im_graph_free(g) -> None:
     lib().im_graph_free(g)
 
@@ -140,6 +155,13 @@ def im_sketch_registers(s, n: int, J: int) -> np.ndarray:
     M = np.zeros((n, J), dtype=np.uint8)
     _check(lib().im_sketch_registers(s, _p(M)))
     return M
+
+
+def im_sketch_register_rows(s, rows, J: int) -> np.ndarray:
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    out = np.zeros((rows.size, J), dtype=np.uint8)
+    _check(lib().im_sketch_register_rows(s, _p(rows), rows.size, _p(out)))
+    return out
 
 
 def im_sketch_estimates(s, n: int):
@@ -205,6 +227,9 @@ class Sketch:
 
     def registers(self) -> np.ndarray:
         return im_sketch_registers(self.handle, self.graph.n, self.J)
+
+    def register_rows(self, rows) -> np.ndarray:
+        return im_sketch_register_rows(self.handle, rows, self.J)
 
     def estimates(self):
         return im_sketch_estimates(self.handle, self.graph.n)

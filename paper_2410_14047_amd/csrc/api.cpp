@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -54,12 +55,24 @@ struct Arena {
 int default_split()
 {
     const char* s = std::getenv("IMX_SPLIT");
-    int v = s ? std::atoi(s) : 512;
-    return v >= 64 ? v : 512;
+    int v = s ? std::atoi(s) : 128;
+    return (v >= 16 && v < (1 << 30)) ? v : 128;
+}
+
+// Lane-group size of the propagation kernel: full waves for the first sweep
+// after a fill (every arc active, long runs of work per task), small groups
+// for frontier sweeps (few active arcs per task, many tasks in flight).
+int group_size_for(int sweep)
+{
+    const char* s = std::getenv(sweep == 0 ? "IMX_GROUP_FIRST" : "IMX_GROUP");
+    const int dflt = sweep == 0 ? 64 : 16;
+    return s ? std::atoi(s) : dflt;
 }
 
 constexpr int kSweepBatch = 4;  // sweeps launched between host checks
 constexpr int kLevelBatch = 4;  // cascade levels launched between host checks
+
+std::atomic<int> g_profiling{0};
 
 }  // namespace
 
@@ -71,13 +84,24 @@ struct im_graph {
     uint32_t* W = nullptr;
     int32_t* task_u = nullptr;
     int64_t* task_e0 = nullptr;
+    uint32_t* task_len = nullptr;
+    int32_t* task_start = nullptr;
     int64_t ntasks = 0;
     int32_t split = 512;
+    int64_t* in_rowptr = nullptr;
+    int32_t* in_col = nullptr;
+    int32_t* in_task_v = nullptr;
+    int64_t* in_task_e0 = nullptr;
+    int32_t* in_task_start = nullptr;
+    int64_t n_in_tasks = 0;
+    int32_t in_split = 256;
     Arena arena;
 
     imx::GraphDev dev() const
     {
-        return imx::GraphDev{n, m, rowptr, col, W, task_u, task_e0, ntasks, split};
+        return imx::GraphDev{n,          m,         rowptr,     col,           W,          task_u,
+                             task_e0,    task_len,  task_start, ntasks,        split,      in_rowptr,
+                             in_col,     in_task_v, in_task_e0, in_task_start, n_in_tasks, in_split};
     }
 };
 
@@ -90,8 +114,7 @@ struct im_sketch {
     uint32_t* X = nullptr;
     uint32_t* Ju = nullptr;
     unsigned long long* Hu = nullptr;
-    uint32_t* chg[2] = {nullptr, nullptr};
-    unsigned long long* ctr = nullptr;  // [kSweepBatch] changed-row counters
+    imx::SweepDev sw{};
     uint8_t* is_seed = nullptr;
     int32_t* best = nullptr;
     imx::CascadeDev casc{};
@@ -100,9 +123,12 @@ struct im_sketch {
     uint32_t level_base = 0;
     bool selected = false;
     im_stats st{};
+    imx::PropCounters* pc = nullptr;      // instrumented-kernel counters (profiling 2)
+    int profiling = 0;
     unsigned long long* h_ctr = nullptr;  // pinned
     uint32_t* h_qs = nullptr;             // pinned
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t evk[2 * kSweepBatch] = {};  // per-launch propagation timing
     Arena arena;
 
     ~im_sketch()
@@ -111,6 +137,8 @@ struct im_sketch {
         if (h_ctr) (void)hipHostFree(h_ctr);
         if (h_qs) (void)hipHostFree(h_qs);
         for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+        for (auto& e : evk)
             if (e) (void)hipEventDestroy(e);
     }
 };
@@ -139,24 +167,31 @@ im_status run_build(im_sketch* s, bool first, int32_t* sweeps_out)
     const size_t bm_bytes = (size_t)((g->n + 31) / 32) * 4;
     hipStream_t st = s->stream;
     IMX_HIP(imx::launch_fill(s->M, g->n, s->J, s->seed, first, st));
-    IMX_HIP(hipMemsetAsync(s->chg[0], 0xff, bm_bytes, st));
+    IMX_HIP(hipMemsetAsync(s->sw.chg[0], 0xff, bm_bytes, st));  // every row counts as changed
+    if (s->pc) IMX_HIP(hipMemsetAsync(s->pc, 0, sizeof(imx::PropCounters), st));
     IMX_HIP(hipEventRecord(s->ev[2], st));
-    int cur = 0;
-    int64_t sweeps = 0;
+    int64_t sweeps = 0, launches = 0;
     bool done = false;
     const imx::GraphDev gd = g->dev();
+    int sweep = 0;
     while (!done) {
-        for (int b = 0; b < kSweepBatch; ++b) {
-            IMX_HIP(hipMemsetAsync(s->chg[1 - cur], 0, bm_bytes, st));
-            IMX_HIP(hipMemsetAsync(s->ctr + b, 0, sizeof(unsigned long long), st));
-            IMX_HIP(imx::launch_propagate(gd, s->X, s->J, s->M, s->chg[cur], s->chg[1 - cur], s->ctr + b, st));
-            cur = 1 - cur;
+        for (int b = 0; b < kSweepBatch; ++b, ++sweep) {
+            IMX_HIP(imx::launch_sweep_prep(s->sw, g->n, sweep, st));
+            IMX_HIP(hipEventRecord(s->evk[2 * b], st));
+            IMX_HIP(imx::launch_propagate(gd, s->X, s->J, s->M, s->sw, sweep, group_size_for(sweep), s->pc, st));
+            IMX_HIP(hipEventRecord(s->evk[2 * b + 1], st));
+            IMX_HIP(imx::launch_mark(gd, s->sw, sweep, st));
         }
-        IMX_HIP(hipMemcpyAsync(s->h_ctr, s->ctr, sizeof(unsigned long long) * kSweepBatch, hipMemcpyDeviceToHost, st));
+        IMX_HIP(hipMemcpyAsync(s->h_ctr, s->sw.rows_changed, sizeof(unsigned long long) * 4, hipMemcpyDeviceToHost,
+                               st));
         IMX_HIP(hipStreamSynchronize(st));
         for (int b = 0; b < kSweepBatch; ++b) {
+            s->st.prop_kernel_ms += elapsed(s->evk[2 * b], s->evk[2 * b + 1]);
+            ++launches;
+        }
+        for (int b = 0; b < kSweepBatch; ++b) {
             ++sweeps;
-            if (s->h_ctr[b] == 0) {
+            if (s->h_ctr[(sweep - kSweepBatch + b) & 3] == 0) {
                 done = true;
                 break;
             }
@@ -166,6 +201,21 @@ im_status run_build(im_sketch* s, bool first, int32_t* sweeps_out)
     IMX_HIP(hipEventRecord(s->ev[3], st));
     IMX_HIP(imx::launch_estimate(s->M, g->n, s->J, s->Ju, s->Hu, st));
     IMX_HIP(hipStreamSynchronize(st));
+    s->st.prop_launches += launches;
+    if (s->pc) {
+        imx::PropCounters c{};
+        IMX_HIP(hipMemcpyAsync(&c, s->pc, sizeof(c), hipMemcpyDeviceToHost, st));
+        IMX_HIP(hipStreamSynchronize(st));
+        s->st.prop_tasks += (int64_t)c.tasks;
+        s->st.prop_rows_read += (int64_t)c.rows_read;
+        s->st.prop_bytes_written += (int64_t)c.bytes_written;
+        s->st.prop_arcs_scanned += (int64_t)c.arcs_scanned;
+        s->st.prop_arcs_active += (int64_t)c.arcs_active;
+        s->st.prop_sectors += (int64_t)c.sectors;
+        s->st.prop_alg_bytes += 28.0 * c.tasks + 4.0 * c.arcs_scanned + 4.0 * c.arcs_active + 64.0 * c.sectors +
+                                (double)s->J * c.rows_read + (double)c.bytes_written +
+                                (double)((g->n + 31) / 32) * 4.0 * 2.0 * launches;
+    }
     s->st.propagate_ms += elapsed(s->ev[2], s->ev[3]);
     s->st.total_sweeps += sweeps;
     if (sweeps_out) *sweeps_out = (int32_t)sweeps;
@@ -182,6 +232,13 @@ im_status im_version(int32_t* major, int32_t* minor)
 {
     if (major) *major = 0;
     if (minor) *minor = 1;
+    return IM_OK;
+}
+
+im_status im_set_profiling(int32_t level)
+{
+    if (level != 0 && level != 2) return fail(IM_EINVAL, "profiling level must be 0 or 2");
+    g_profiling.store(level);
     return IM_OK;
 }
 
@@ -210,15 +267,44 @@ im_status im_graph_load(int64_t n, int64_t m, const int64_t* rowptr_host, const 
     if (im_status e = check_device()) return e;
 
     const int split = default_split();
-    std::vector<int32_t> tu;
+    const int in_split = 256;
+    std::vector<int32_t> tu, ts(n + 1);
     std::vector<int64_t> te;
-    for (int64_t u = 0; u < n; ++u)
+    std::vector<uint32_t> tl;
+    for (int64_t u = 0; u < n; ++u) {
+        ts[u] = (int32_t)tu.size();
+        const int64_t deg = rowptr_host[u + 1] - rowptr_host[u];
         for (int64_t e0 = rowptr_host[u]; e0 < rowptr_host[u + 1]; e0 += split) {
             tu.push_back((int32_t)u);
             te.push_back(e0);
+            const int64_t len = std::min<int64_t>(split, rowptr_host[u + 1] - e0);
+            tl.push_back((uint32_t)len | (deg > split ? 0x80000000u : 0u));
         }
+    }
+    ts[n] = (int32_t)tu.size();
+    if ((int64_t)tu.size() >= (int64_t(1) << 31)) return fail(IM_EINVAL, "too many propagation tasks");
+    // reverse graph: in-arcs of every vertex, sources ascending
+    std::vector<int64_t> irp(n + 1, 0);
+    for (int64_t e = 0; e < m; ++e) ++irp[col_host[e] + 1];
+    for (int64_t v = 0; v < n; ++v) irp[v + 1] += irp[v];
+    std::vector<int32_t> icol(m);
+    {
+        std::vector<int64_t> pos(irp.begin(), irp.end() - 1);
+        for (int64_t u = 0; u < n; ++u)
+            for (int64_t e = rowptr_host[u]; e < rowptr_host[u + 1]; ++e) icol[pos[col_host[e]]++] = (int32_t)u;
+    }
+    std::vector<int32_t> itv, its(n + 1);
+    std::vector<int64_t> ite;
+    for (int64_t v = 0; v < n; ++v) {
+        its[v] = (int32_t)itv.size();
+        for (int64_t e0 = irp[v]; e0 < irp[v + 1]; e0 += in_split) {
+            itv.push_back((int32_t)v);
+            ite.push_back(e0);
+        }
+    }
+    its[n] = (int32_t)itv.size();
 
-    size_t need = sizeof(int64_t) * (n + 1) + (size_t)m * 12 + tu.size() * 12;
+    size_t need = sizeof(int64_t) * (n + 1) * 2 + (size_t)m * 16 + tu.size() * 12 + itv.size() * 12 + (size_t)n * 8;
     size_t free_b = 0, total_b = 0;
     IMX_HIP(hipMemGetInfo(&free_b, &total_b));
     if (need + (64u << 20) > free_b) return fail(IM_ENOMEM, "graph does not fit in device memory");
@@ -229,6 +315,8 @@ im_status im_graph_load(int64_t n, int64_t m, const int64_t* rowptr_host, const 
     g->m = m;
     g->split = split;
     g->ntasks = (int64_t)tu.size();
+    g->in_split = in_split;
+    g->n_in_tasks = (int64_t)itv.size();
     float* p_dev = nullptr;
     auto cleanup = [&](im_status st, const std::string& msg) {
         if (p_dev) (void)hipFree(p_dev);
@@ -236,9 +324,11 @@ im_status im_graph_load(int64_t n, int64_t m, const int64_t* rowptr_host, const 
         delete g;
         return fail(st, msg);
     };
-    if (g->arena.alloc(&g->rowptr, n + 1) || g->arena.alloc(&g->col, m) || g->arena.alloc(&g->W, m) ||
-        g->arena.alloc(&g->task_u, tu.size()) || g->arena.alloc(&g->task_e0, te.size()) ||
-        hipMalloc(&p_dev, std::max<size_t>(m * sizeof(float), 1)) != hipSuccess)
+    Arena& A = g->arena;
+    if (A.alloc(&g->rowptr, n + 1) || A.alloc(&g->col, m) || A.alloc(&g->W, m) || A.alloc(&g->task_u, tu.size()) ||
+        A.alloc(&g->task_e0, te.size()) || A.alloc(&g->task_len, tl.size()) || A.alloc(&g->task_start, n + 1) || A.alloc(&g->in_rowptr, n + 1) ||
+        A.alloc(&g->in_col, m) || A.alloc(&g->in_task_v, itv.size()) || A.alloc(&g->in_task_e0, ite.size()) ||
+        A.alloc(&g->in_task_start, n + 1) || hipMalloc(&p_dev, std::max<size_t>(m * sizeof(float), 1)) != hipSuccess)
         return cleanup(IM_ENOMEM, "device allocation failed");
     hipStream_t st = g->stream;
     hipError_t e = hipMemcpyAsync(g->rowptr, rowptr_host, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, st);
@@ -248,6 +338,20 @@ im_status im_graph_load(int64_t n, int64_t m, const int64_t* rowptr_host, const 
         e = hipMemcpyAsync(g->task_u, tu.data(), sizeof(int32_t) * tu.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess && !te.empty())
         e = hipMemcpyAsync(g->task_e0, te.data(), sizeof(int64_t) * te.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !tl.empty())
+        e = hipMemcpyAsync(g->task_len, tl.data(), sizeof(uint32_t) * tl.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->task_start, ts.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->in_rowptr, irp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && m)
+        e = hipMemcpyAsync(g->in_col, icol.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !itv.empty())
+        e = hipMemcpyAsync(g->in_task_v, itv.data(), sizeof(int32_t) * itv.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !ite.empty())
+        e = hipMemcpyAsync(g->in_task_e0, ite.data(), sizeof(int64_t) * ite.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->in_task_start, its.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = imx::launch_thresholds(p_dev, g->W, m, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return cleanup(IM_EDEVICE, std::string("graph upload: ") + hipGetErrorString(e));
@@ -282,7 +386,8 @@ im_status im_sketch_build(const im_graph* g, int32_t J, uint64_t seed, void* str
     const int64_t n = g->n;
     const size_t nJ = (size_t)n * (size_t)J;
     const size_t bm_words = (size_t)((n + 31) / 32);
-    size_t need = nJ + (size_t)n * (4 + 8 + 1 + 4 * 5) + bm_words * 8 + (1u << 20);
+    const size_t nt = (size_t)std::max<int64_t>(g->ntasks, 1), nit = (size_t)std::max<int64_t>(g->n_in_tasks, 1);
+    size_t need = nJ + (size_t)n * (4 + 8 + 1 + 4 * 3) + bm_words * 12 + nt * 16 + nit * 4 + (1u << 20);
     size_t free_b = 0, total_b = 0;
     IMX_HIP(hipMemGetInfo(&free_b, &total_b));
     if (need + (64u << 20) > free_b) return fail(IM_ENOMEM, "sketch does not fit in device memory");
@@ -298,18 +403,24 @@ im_status im_sketch_build(const im_graph* g, int32_t J, uint64_t seed, void* str
     };
     Arena& A = s->arena;
     if (A.alloc(&s->M, nJ) || A.alloc(&s->X, J) || A.alloc(&s->Ju, n) || A.alloc(&s->Hu, n) ||
-        A.alloc(&s->chg[0], bm_words) || A.alloc(&s->chg[1], bm_words) || A.alloc(&s->ctr, kSweepBatch) ||
-        A.alloc(&s->is_seed, n) || A.alloc(&s->best, 1) || A.alloc(&s->casc.q[0], n) || A.alloc(&s->casc.q[1], n) ||
+        A.alloc(&s->sw.chg[0], bm_words) || A.alloc(&s->sw.chg[1], bm_words) || A.alloc(&s->sw.act_bm, bm_words) ||
+        A.alloc(&s->sw.act_tasks[0], nt) || A.alloc(&s->sw.act_tasks[1], nt) || A.alloc(&s->sw.act_count, 4) ||
+        A.alloc(&s->sw.chg_list, nit) || A.alloc(&s->sw.chg_count, 4) || A.alloc(&s->sw.rows_changed, 4) ||
+        A.alloc(&s->is_seed, n) || A.alloc(&s->best, 1) || A.alloc(&s->casc.q[0], nt) || A.alloc(&s->casc.q[1], nt) ||
         A.alloc(&s->casc.qsize, 4) || A.alloc(&s->casc.stamp, n) || A.alloc(&s->casc.touched, n) ||
         A.alloc(&s->casc.ntouched, 1) || A.alloc(&s->casc.touch_stamp, n) || A.alloc(&s->casc.T, 1) ||
         A.alloc(&s->am.pJ, imx::kArgmaxBlocks) || A.alloc(&s->am.pH, imx::kArgmaxBlocks) ||
         A.alloc(&s->am.pid, imx::kArgmaxBlocks))
         return bad(IM_ENOMEM, "device allocation failed");
-    if (hipHostMalloc(reinterpret_cast<void**>(&s->h_ctr), sizeof(unsigned long long) * kSweepBatch, 0) != hipSuccess ||
+    if (hipHostMalloc(reinterpret_cast<void**>(&s->h_ctr), sizeof(unsigned long long) * 4, 0) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&s->h_qs), sizeof(uint32_t) * 4, 0) != hipSuccess)
         return bad(IM_ENOMEM, "pinned host allocation failed");
     for (auto& e : s->ev)
         if (hipEventCreate(&e) != hipSuccess) return bad(IM_EDEVICE, "hipEventCreate failed");
+    for (auto& e : s->evk)
+        if (hipEventCreate(&e) != hipSuccess) return bad(IM_EDEVICE, "hipEventCreate failed");
+    s->profiling = g_profiling.load();
+    if (s->profiling >= 2 && A.alloc(&s->pc, 1)) return bad(IM_ENOMEM, "device allocation failed");
 
     hipStream_t st = s->stream;
     hipError_t e = hipMemsetAsync(s->is_seed, 0, n, st);
@@ -378,8 +489,8 @@ im_status im_select_seeds(im_sketch* s, int32_t K, int32_t* seeds_host, double* 
         IMX_HIP(hipEventRecord(c0, st));
         const uint32_t cid = ++s->cascade_id;
         const uint32_t base = s->level_base;
-        IMX_HIP(imx::launch_cascade_seed(s->best, k, s->M, s->J, s->is_seed, seeds_dev, pickJ, pickH, s->Ju, s->Hu,
-                                         s->casc, cid, base + 1, st));
+        IMX_HIP(imx::launch_cascade_seed(gd, s->best, k, s->M, s->J, s->is_seed, seeds_dev, pickJ, pickH, s->Ju,
+                                         s->Hu, s->casc, cid, base + 1, st));
         int t = 1;
         for (;;) {
             for (int b = 0; b < kLevelBatch; ++b, ++t)
@@ -444,6 +555,19 @@ im_status im_sketch_registers(const im_sketch* s, uint8_t* regs_host)
 {
     if (!s || !regs_host) return fail(IM_EINVAL, "NULL argument");
     IMX_HIP(hipMemcpyAsync(regs_host, s->M, (size_t)s->g->n * (size_t)s->J, hipMemcpyDeviceToHost, s->stream));
+    IMX_HIP(hipStreamSynchronize(s->stream));
+    return IM_OK;
+}
+
+im_status im_sketch_register_rows(const im_sketch* s, const int32_t* rows_host, int32_t nrows, uint8_t* regs_host)
+{
+    if (!s || nrows < 0 || (nrows > 0 && (!rows_host || !regs_host))) return fail(IM_EINVAL, "NULL argument");
+    for (int32_t i = 0; i < nrows; ++i)
+        if (rows_host[i] < 0 || rows_host[i] >= s->g->n) return fail(IM_EINVAL, "row id out of range");
+    const size_t J = (size_t)s->J;
+    for (int32_t i = 0; i < nrows; ++i)
+        IMX_HIP(hipMemcpyAsync(regs_host + (size_t)i * J, s->M + (size_t)rows_host[i] * J, J, hipMemcpyDeviceToHost,
+                               s->stream));
     IMX_HIP(hipStreamSynchronize(s->stream));
     return IM_OK;
 }

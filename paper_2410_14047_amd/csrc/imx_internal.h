@@ -7,34 +7,71 @@
 
 namespace imx {
 
-constexpr int kWaves = 4;             // waves per workgroup in the wave-per-row kernels
+constexpr int kWaves = 4;             // waves per workgroup in the wave-per-task kernels
 constexpr int kWG = 64 * kWaves;      // workgroup size
 constexpr int kMaxJ = 4096;           // registers per vertex, upper bound
 constexpr int kArgmaxBlocks = 1024;   // partial-argmax workgroups
 
-// Device view of a loaded graph plus its propagation work list: every vertex
-// with out-degree > 0 owns ceil(deg / split) tasks, each a run of at most
-// `split` consecutive out-arcs.
+// Device view of a loaded graph and its work decomposition.
+//   Out-tasks: every vertex u with out-degree > 0 owns the tasks
+//   task_start[u] .. task_start[u+1]-1, each a run of at most `split`
+//   consecutive out-arcs starting at task_e0[t].
+//   In-tasks: the same over the reverse graph (in-arcs of v, sources in
+//   in_col), runs of at most `in_split` in-arcs.
 struct GraphDev {
     int64_t n, m;
-    const int64_t* rowptr;   // [n+1]
-    const int32_t* col;      // [m]
-    const uint32_t* W;       // [m] 31-bit fixed-point thresholds
-    const int32_t* task_u;   // [ntasks] source vertex of the task
-    const int64_t* task_e0;  // [ntasks] first arc of the task
+    const int64_t* rowptr;        // [n+1]
+    const int32_t* col;           // [m]
+    const uint32_t* W;            // [m] 31-bit fixed-point thresholds
+    const int32_t* task_u;        // [ntasks]
+    const int64_t* task_e0;       // [ntasks]
+    const uint32_t* task_len;     // [ntasks] arcs in the task; bit 31 set when u has several tasks
+    const int32_t* task_start;    // [n+1]
     int64_t ntasks;
-    int32_t split;           // max arcs per task
+    int32_t split;
+    const int64_t* in_rowptr;     // [n+1]
+    const int32_t* in_col;        // [m] source of each in-arc
+    const int32_t* in_task_v;     // [n_in_tasks]
+    const int64_t* in_task_e0;    // [n_in_tasks]
+    const int32_t* in_task_start; // [n+1]
+    int64_t n_in_tasks;
+    int32_t in_split;
 };
 
-// Device state of the covering cascade (union-frontier BFS).
+// Device state of the propagation sweeps.  Sweep s reads chg[s&1] (rows that
+// changed in sweep s-1) and the active task list act_tasks[s&1] (count
+// act_count[s&3]); it writes chg[(s+1)&1], the in-tasks of its changed rows
+// (chg_list, count chg_count[s&3]) and rows_changed[s&3].  The mark step of
+// sweep s turns chg_list into act_tasks[(s+1)&1] / act_count[(s+1)&3].
+struct SweepDev {
+    int32_t* act_tasks[2];            // [ntasks] each
+    uint32_t* act_count;              // [4]
+    uint32_t* chg[2];                 // [ceil(n/32)] each
+    uint32_t* act_bm;                 // [ceil(n/32)] vertices already activated
+    int32_t* chg_list;                // [n_in_tasks]
+    uint32_t* chg_count;              // [4]
+    unsigned long long* rows_changed; // [4]
+};
+
+// Device state of the covering cascade (union-frontier BFS over tasks).
 struct CascadeDev {
-    int32_t* q[2];           // frontier queues, capacity n each
-    uint32_t* qsize;         // ring of 4 queue-size counters
+    int32_t* q[2];           // frontier out-task lists, capacity ntasks each
+    uint32_t* qsize;         // ring of 4 list-size counters
     uint32_t* stamp;         // [n] id of the last frontier v was appended to
     int32_t* touched;        // [n] distinct vertices touched by this cascade
     uint32_t* ntouched;      // counter for `touched`
     uint32_t* touch_stamp;   // [n] id of the last cascade that touched v
     unsigned long long* T;   // covered (vertex, simulation) pairs
+};
+
+// Event counts of the instrumented propagation kernel (algorithmic traffic).
+struct PropCounters {
+    unsigned long long tasks;          // tasks visited
+    unsigned long long rows_read;      // rows of u read (J bytes each)
+    unsigned long long bytes_written;  // register bytes stored (changed 32-bit words x 4)
+    unsigned long long arcs_scanned;   // arcs whose head id was read
+    unsigned long long arcs_active;    // arcs whose head changed in the previous sweep
+    unsigned long long sectors;        // distinct 64-byte sectors of head rows holding live registers
 };
 
 struct ArgmaxScratch {
@@ -46,16 +83,19 @@ struct ArgmaxScratch {
 hipError_t launch_thresholds(const float* p, uint32_t* W, int64_t m, hipStream_t st);
 hipError_t launch_sim_values(uint64_t seed, int J, uint32_t* X, hipStream_t st);
 hipError_t launch_fill(uint8_t* M, int64_t n, int J, uint64_t seed, bool first, hipStream_t st);
-hipError_t launch_propagate(const GraphDev& g, const uint32_t* X, int J, uint8_t* M, const uint32_t* chg_prev,
-                            uint32_t* chg_next, unsigned long long* changed, hipStream_t st);
+hipError_t launch_sweep_prep(const SweepDev& s, int64_t n, int sweep, hipStream_t st);
+int propagate_group_size(int J, int requested);
+hipError_t launch_propagate(const GraphDev& g, const uint32_t* X, int J, uint8_t* M, const SweepDev& s, int sweep,
+                            int group_size, PropCounters* stats, hipStream_t st);
+hipError_t launch_mark(const GraphDev& g, const SweepDev& s, int sweep, hipStream_t st);
 hipError_t launch_estimate(const uint8_t* M, int64_t n, int J, uint32_t* Ju, unsigned long long* Hu,
                            hipStream_t st);
 hipError_t launch_argmax(const uint32_t* Ju, const unsigned long long* Hu, const uint8_t* is_seed, int64_t n,
                          const ArgmaxScratch& s, int32_t* best, hipStream_t st);
-hipError_t launch_cascade_seed(const int32_t* best, int32_t k, uint8_t* M, int J, uint8_t* is_seed,
-                               int32_t* seeds, uint32_t* pickJ, unsigned long long* pickH, const uint32_t* Ju,
-                               const unsigned long long* Hu, const CascadeDev& c, uint32_t cascade_id,
-                               uint32_t level_id1, hipStream_t st);
+hipError_t launch_cascade_seed(const GraphDev& g, const int32_t* best, int32_t k, uint8_t* M, int J,
+                               uint8_t* is_seed, int32_t* seeds, uint32_t* pickJ, unsigned long long* pickH,
+                               const uint32_t* Ju, const unsigned long long* Hu, const CascadeDev& c,
+                               uint32_t cascade_id, uint32_t level_id1, hipStream_t st);
 hipError_t launch_cascade_level(const GraphDev& g, const uint32_t* X, int J, uint8_t* M, const CascadeDev& c,
                                 int t, uint32_t level_id, uint32_t cascade_id, hipStream_t st);
 hipError_t launch_cascade_finalize(uint8_t* M, int J, uint32_t* Ju, unsigned long long* Hu, const CascadeDev& c,

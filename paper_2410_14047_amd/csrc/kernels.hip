@@ -139,31 +139,112 @@ __device__ __forceinline__ int owner_of(const int* start, int idx)
     return k;
 }
 
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// Byte-wise max of four packed registers (values < 256): even and odd bytes
+// are compared as two packed 16-bit lanes each.
 __device__ __forceinline__ uint32_t bytemax4(uint32_t a, uint32_t b)
 {
-    uint32_t r = 0;
-#pragma unroll
-    for (int s = 0; s < 32; s += 8) {
-        uint32_t x = (a >> s) & 0xffu, y = (b >> s) & 0xffu;
-        r |= (x > y ? x : y) << s;
-    }
-    return r;
+    const u16x2 ae = __builtin_bit_cast(u16x2, a & 0x00ff00ffu), be = __builtin_bit_cast(u16x2, b & 0x00ff00ffu);
+    const u16x2 ao = __builtin_bit_cast(u16x2, (a >> 8) & 0x00ff00ffu);
+    const u16x2 bo = __builtin_bit_cast(u16x2, (b >> 8) & 0x00ff00ffu);
+    const uint32_t e = __builtin_bit_cast(uint32_t, __builtin_elementwise_max(ae, be));
+    const uint32_t o = __builtin_bit_cast(uint32_t, __builtin_elementwise_max(ao, bo));
+    return e | (o << 8);
 }
 
-// Wave-aggregated append of `v` (lanes with push) to queue Q with counter ctr.
-__device__ __forceinline__ void wave_append(bool push, int32_t v, int32_t* Q, uint32_t* ctr)
+// 0xff in byte b iff simulation x4[b] has the arc (hash h, threshold W) live (Eq. 2).
+__device__ __forceinline__ uint32_t live_mask4(uint4 x4, uint32_t h, uint32_t W)
+{
+    return ((x4.x ^ h) < W ? 0x000000ffu : 0u) | ((x4.y ^ h) < W ? 0x0000ff00u : 0u) |
+           ((x4.z ^ h) < W ? 0x00ff0000u : 0u) | ((x4.w ^ h) < W ? 0xff000000u : 0u);
+}
+
+// 0xff in byte b iff byte b of d equals v.
+__device__ __forceinline__ uint32_t eq_mask4(uint32_t d, uint32_t v)
+{
+    uint32_t m = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+        if (((d >> (8 * b)) & 0xffu) == v) m |= 0xffu << (8 * b);
+    return m;
+}
+
+// 0xff in byte b iff byte b of d is an uncovered register (rank 1..33).
+__device__ __forceinline__ uint32_t uncovered_mask4(uint32_t d)
+{
+    uint32_t m = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const uint32_t r = (d >> (8 * b)) & 0xffu;
+        if (r >= 1u && r <= 33u) m |= 0xffu << (8 * b);
+    }
+    return m;
+}
+
+__device__ __forceinline__ uint32_t pack4(uint4 w) { return w.x | (w.y << 8) | (w.z << 16) | (w.w << 24); }
+
+// Per-wave staging buffer in LDS for appends to a global list: ids appended by
+// the lanes are collected and written out in batches, so the list's counter
+// takes one atomic per batch instead of one per append.
+constexpr int kWaveBufCap = 256;
+
+struct WaveList {
+    int32_t* buf;   // LDS staging area of `cap` entries
+    int n;          // staged entries (wave-uniform)
+    int32_t* L;     // global list
+    uint32_t* ctr;  // global count
+    int cap = kWaveBufCap;
+};
+
+__device__ __forceinline__ void wl_flush(WaveList& w)
+{
+    if (w.n == 0) return;
+    wave_lds_sync();
+    uint32_t base = 0;
+    if (lane_id() == 0) base = atomicAdd(w.ctr, (uint32_t)w.n);
+    base = __shfl(base, 0, 64);
+    for (int i = lane_id(); i < w.n; i += 64) w.L[base + i] = w.buf[i];
+    w.n = 0;
+    wave_lds_sync();
+}
+
+// Append ids first..first+cnt-1 of every lane (cnt may differ per lane, 0 = none).
+__device__ __forceinline__ void wl_append_ranges(WaveList& w, int cnt, int32_t first)
 {
     const int lane = lane_id();
-    unsigned long long bal = __ballot(push);
-    if (bal == 0ull) return;
-    int leader = __ffsll((long long)bal) - 1;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(ctr, (uint32_t)__popcll(bal));
-    base = __shfl(base, leader, 64);
-    if (push) {
-        uint32_t off = (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
-        Q[base + off] = v;
+    const int incl = wave_incl_scan(cnt);
+    const int total = __shfl(incl, 63, 64);
+    if (total == 0) return;
+    if (total > w.cap) {
+        uint32_t base = 0;
+        if (lane == 63) base = atomicAdd(w.ctr, (uint32_t)total);
+        base = __shfl(base, 63, 64);
+        const uint32_t off = base + (uint32_t)(incl - cnt);
+        for (int q = 0; q < cnt; ++q) w.L[off + q] = first + q;
+        return;
     }
+    if (w.n + total > w.cap) wl_flush(w);
+    const int off = w.n + incl - cnt;
+    for (int q = 0; q < cnt; ++q) w.buf[off + q] = first + q;
+    w.n += total;
+}
+
+// Append ids first..first+cnt-1 where cnt and first are the same in every lane.
+__device__ __forceinline__ void wl_append_uniform(WaveList& w, int cnt, int32_t first)
+{
+    const int lane = lane_id();
+    if (cnt <= 0) return;
+    if (cnt > w.cap) {
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(w.ctr, (uint32_t)cnt);
+        base = __shfl(base, 0, 64);
+        for (int q = lane; q < cnt; q += 64) w.L[base + q] = first + q;
+        return;
+    }
+    if (w.n + cnt > w.cap) wl_flush(w);
+    for (int q = lane; q < cnt; q += 64) w.buf[w.n + q] = first + q;
+    w.n += cnt;
 }
 
 // ---------------------------------------------------------------------------
@@ -266,186 +347,520 @@ hipError_t launch_fill(uint8_t* M, int64_t n, int J, uint64_t seed, bool first, 
 }
 
 // ---------------------------------------------------------------------------
-// a4: one propagation sweep (Alg. 2, pull-based, in place).
+// a4: propagation sweeps (Alg. 2, pull-based, in place), frontier-driven.
 //
-// One wave per task (a vertex u, or a run of at most `split` of its out-arcs).
-// Lane-per-arc phase: arc hash, threshold, candidate range from sorted X, and
-// the frontier filter (only arcs whose head changed in the previous sweep).
-// Flattened phase: the (arc, candidate simulation) pairs of 64 arcs are dealt
-// to lanes; each lane tests liveness (Eq. 2) and max-merges the head's
-// register into u's row, kept as one 32-bit word per simulation in LDS.
-// Finally the row is packed to bytes; changed words are stored (split rows
-// merge with a byte-max compare-and-swap) and u is flagged in chg_next.
+// Work unit: a task = a vertex u, or a run of at most `split` of its out-arcs.
+// Each wave is cut into lane groups of GS lanes (GS = 16, 32 or 64); every
+// group owns one task, so a wave has 64/GS independent dependency chains in
+// flight.  Per task:
+//   - lane-per-arc phase: for arcs whose head v changed in the previous sweep,
+//     the arc hash (Eq. 1), threshold, and the candidate range [lo, hi) of
+//     sorted X that holds every simulation the arc can be live in;
+//   - u's row is staged in LDS as bytes; dense arcs (at least J/2 candidates)
+//     are merged by the whole group, each lane owning fixed 32-bit words;
+//     sparse arcs are flattened into (arc, word) items dealt to the group's
+//     lanes.  Every merge is a byte-wise max (Eq. 5) of the head's word masked
+//     to the simulations where the arc is live (Eq. 2).  Items of one round may
+//     hit the same LDS word; a read-max-write-verify loop settles them (the
+//     last writer among colliding lanes exits each round, so it terminates);
+//   - changed words (tracked in a per-group dirty bitmap) are stored to HBM;
+//     rows split over several tasks merge with a byte-max compare-and-swap.
+//     A changed row u is flagged in the next changed bitmap, and the vertices
+//     that pull from u are activated for the next sweep: directly by the group
+//     when u has few in-arcs, otherwise through u's in-tasks and k_mark.
 
 struct PropArgs {
     GraphDev g;
     const uint32_t* X;
     int J;
     uint8_t* M;
+    const int32_t* tasks;         // active tasks (nullptr: every task)
+    const uint32_t* task_count;   // device count of `tasks`
     const uint32_t* chg_prev;
     uint32_t* chg_next;
-    unsigned long long* changed;
+    int32_t* chg_list;
+    uint32_t* chg_count;
+    uint32_t* act_bm;
+    int32_t* act_next;
+    uint32_t* act_next_count;
+    unsigned long long* rows_changed;
+    PropCounters* stats;          // instrumented variant only
 };
 
-constexpr int kEdgeBufWords = 5 * 64;
+constexpr int kDirectMark = 64;   // in-degree up to which a changed row activates its pullers itself
+constexpr int kPropBufCap = 128;  // staging entries per wave and list
 
-template <int DPL>
+// LDS words per group besides the row: arc arrays (5 x GS), dirty bitmap
+// (Jw/32 <= 32 words), and (instrumented variant) sector masks (2 x GS).
+template <int GS, bool STATS>
+constexpr int group_buf_words()
+{
+    return 5 * GS + 32 + (STATS ? 2 * GS : 0);
+}
+
+__device__ __forceinline__ unsigned long long group_mask(int gbase, int GS)
+{
+    return (GS == 64) ? ~0ull : (((1ull << GS) - 1ull) << gbase);
+}
+
+template <int GS>
+__device__ __forceinline__ int group_incl_scan(int x, int lig)
+{
+#pragma unroll
+    for (int d = 1; d < GS; d <<= 1) {
+        int y = __shfl_up(x, d, GS);
+        if (lig >= d) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ int wave_max_i32(int x)
+{
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        const int y = __shfl_xor(x, d, 64);
+        x = x > y ? x : y;
+    }
+    return x;
+}
+
+// Largest k in [0,GS) with start[k] <= idx (start non-decreasing, start[0] = 0).
+template <int GS>
+__device__ __forceinline__ int group_owner(const int* start, int idx)
+{
+    int k = 0;
+#pragma unroll
+    for (int step = GS / 2; step > 0; step >>= 1)
+        if (start[k + step] <= idx) k += step;
+    return k;
+}
+
+// Byte-wise max of `val` into LDS word w (index d) for lanes with `pending`;
+// lanes of one wave may collide on a word.  Each pass, every colliding lane
+// whose value the word already dominates leaves, and the lane whose write
+// landed last always does, so the loop ends after at most 64 passes.
+__device__ __forceinline__ void lds_merge_word(uint32_t* w, uint32_t* dirty, int d, uint32_t val, bool pending)
+{
+    while (__ballot(pending) != 0ull) {
+        if (pending) {
+            const uint32_t cur = *w;
+            const uint32_t want = bytemax4(cur, val);
+            if (want == cur) {
+                pending = false;
+            } else {
+                *w = want;
+                atomicOr(&dirty[d >> 5], 1u << (d & 31));
+            }
+        }
+        wave_lds_sync();
+    }
+}
+
+template <int GS, int DPLG, bool STATS>
 __global__ __launch_bounds__(kWG) void k_propagate(PropArgs a)
 {
+    constexpr int NG = 64 / GS;
+    constexpr int GB = group_buf_words<GS, STATS>();
     extern __shared__ uint32_t smem[];
     const int J = a.J;
-    const int Jw = J >> 2;  // 32-bit words per row
+    const int Jw = J >> 2;
     const int wave = (int)(threadIdx.x >> 6);
     const int lane = lane_id();
+    const int gi = lane / GS, lig = lane % GS, gbase = gi * GS;
+    const unsigned long long gmask = group_mask(gbase, GS);
+
     uint32_t* sX = smem;
-    uint32_t* row = smem + J + wave * (J + kEdgeBufWords);
-    int* ev = reinterpret_cast<int*>(row + J);
-    uint32_t* eh = row + J + 64;
-    uint32_t* eW = row + J + 128;
-    int* elo = reinterpret_cast<int*>(row + J + 192);
-    int* est = reinterpret_cast<int*>(row + J + 256);
+    int32_t* wbuf = reinterpret_cast<int32_t*>(smem + J + wave * 2 * kPropBufCap);
+    uint32_t* gbuf = smem + J + kWaves * 2 * kPropBufCap + (wave * NG + gi) * (Jw + GB);
+    uint32_t* rowW = gbuf;  // Jw words = J register bytes
+    int* ev = reinterpret_cast<int*>(gbuf + Jw);
+    uint32_t* eh = gbuf + Jw + GS;
+    uint32_t* eW = gbuf + Jw + 2 * GS;
+    int* edl = reinterpret_cast<int*>(gbuf + Jw + 3 * GS);
+    int* est = reinterpret_cast<int*>(gbuf + Jw + 4 * GS);
+    uint32_t* dirty = gbuf + Jw + 5 * GS;
+    unsigned long long* esec = reinterpret_cast<unsigned long long*>(gbuf + Jw + 5 * GS + 32);  // STATS only
+    WaveList chl{wbuf, 0, a.chg_list, a.chg_count, kPropBufCap};
+    WaveList act{wbuf + kPropBufCap, 0, a.act_next, a.act_next_count, kPropBufCap};
+    unsigned long long c_tasks = 0, c_rows = 0, c_wbytes = 0, c_scanned = 0, c_active = 0, c_sectors = 0;
+    unsigned long long c_changed = 0;
 
     for (int i = threadIdx.x; i < J; i += kWG) sX[i] = a.X[i];
     __syncthreads();
 
     const GraphDev& g = a.g;
-    const int64_t nw = (int64_t)gridDim.x * kWaves;
-    for (int64_t t = (int64_t)blockIdx.x * kWaves + wave; t < g.ntasks; t += nw) {
-        const int32_t u = g.task_u[t];
-        const int64_t rb = g.rowptr[u], re = g.rowptr[u + 1];
-        const int64_t e0 = g.task_e0[t];
-        const int64_t e1 = (e0 + g.split < re) ? e0 + g.split : re;
-        const bool split = (re - rb) > (int64_t)g.split;
-        uint8_t* Mu = a.M + (size_t)u * (size_t)J;
-        uint32_t saved[DPL];
-        bool init = false;
+    const uint32_t* M32 = reinterpret_cast<const uint32_t*>(a.M);
+    uint32_t* MW = reinterpret_cast<uint32_t*>(a.M);
+    const int64_t count = a.tasks ? (int64_t)*a.task_count : g.ntasks;
+    const int64_t ngroups = (int64_t)gridDim.x * kWaves * NG;
 
-        for (int64_t cb = e0; cb < e1; cb += 64) {
-            const int64_t e = cb + lane;
-            int cnt = 0, lo = 0;
+    for (int64_t qb = ((int64_t)blockIdx.x * kWaves + wave) * NG; qb < count; qb += ngroups) {
+        const int64_t q = qb + gi;
+        const bool valid = q < count;
+        int32_t u = 0;
+        int64_t e0 = 0, e1 = 0;
+        bool split = false;
+        if (valid) {
+            const int32_t t = a.tasks ? a.tasks[q] : (int32_t)q;
+            u = g.task_u[t];
+            e0 = g.task_e0[t];
+            const uint32_t len = g.task_len[t];
+            e1 = e0 + (int64_t)(len & 0x7fffffffu);
+            split = (len >> 31) != 0u;
+        }
+        if (STATS && valid && lig == 0) ++c_tasks;
+        const int nch = valid ? (int)((e1 - e0 + GS - 1) / GS) : 0;
+        const int maxch = wave_max_i32(nch);
+        bool init = false;  // group-uniform
+        for (int c = 0; c < maxch; ++c) {
+            const int64_t e = e0 + (int64_t)c * GS + lig;
+            int cnt = 0, lo = 0, hi = 0;
             int32_t v = 0;
             uint32_t h = 0, w = 0;
+            bool act_arc = false;
             if (e < e1) {
                 v = g.col[e];
-                if ((a.chg_prev[(uint32_t)v >> 5] >> (v & 31)) & 1u) {
-                    w = g.W[e];
+                w = g.W[e];
+                act_arc = (a.chg_prev[(uint32_t)v >> 5] >> (v & 31)) & 1u;
+                if (act_arc && w != 0u) {
                     h = arc_hash((uint32_t)u, (uint32_t)v);
-                    int hi;
                     candidate_range(sX, J, h, w, lo, hi);
                     cnt = hi - lo;
                 }
             }
-            const int incl = wave_incl_scan(cnt);
-            const int total = __shfl(incl, 63, 64);
-            if (total == 0) continue;
-            if (!init) {
-#pragma unroll
-                for (int i = 0; i < DPL; ++i) {
-                    const int idx = lane + 64 * i;
-                    if (idx < Jw) {
-                        uint32_t d = reinterpret_cast<const uint32_t*>(Mu)[idx];
-                        saved[i] = d;
-                        uint4 w4;
-                        w4.x = d & 0xffu;
-                        w4.y = (d >> 8) & 0xffu;
-                        w4.z = (d >> 16) & 0xffu;
-                        w4.w = d >> 24;
-                        *reinterpret_cast<uint4*>(&row[4 * idx]) = w4;
-                    }
-                }
-                init = true;
+            if (STATS) {
+                c_scanned += (e < e1) ? 1ull : 0ull;
+                c_active += act_arc ? 1ull : 0ull;
             }
-            ev[lane] = v;
-            eh[lane] = h;
-            eW[lane] = w;
-            elo[lane] = lo;
-            est[lane] = incl - cnt;
+            const bool gany = (__ballot(cnt > 0) & gmask) != 0ull;
+            if (gany && !init) {
+                // stage u's row in LDS and clear the dirty bitmap
+                const uint32_t* Mu = M32 + (size_t)u * (size_t)Jw;
+#pragma unroll
+                for (int i = 0; i < DPLG; ++i) {
+                    const int idx = lig + GS * i;
+                    if (idx < Jw) rowW[idx] = Mu[idx];
+                }
+                if (lig < 32) dirty[lig] = 0u;
+                if (GS == 16 && lig < 16) dirty[lig + 16] = 0u;
+                init = true;
+                if (STATS && lig == 0) ++c_rows;
+            }
+            const bool dense = cnt > 0 && 2 * cnt >= J;
+            const int nd = (cnt > 0 && !dense) ? (((hi - 1) >> 2) - (lo >> 2) + 1) : 0;
             wave_lds_sync();
-            for (int r = 0; r < total; r += 64) {
-                const int idx = r + lane;
+
+            // dense arcs: the group merges v's row word by word, no collisions
+            unsigned long long rem = (__ballot(dense) & gmask) >> gbase;
+            const int maxd = wave_max_i32(__popcll(rem));
+            for (int k = 0; k < maxd; ++k) {
+                const bool has = rem != 0ull;
+                const int ak = has ? __ffsll((long long)rem) - 1 : 0;
+                rem &= rem - 1ull;
+                const int vk = __shfl(v, gbase + ak, 64);
+                const uint32_t hk = __shfl(h, gbase + ak, 64), wk = __shfl(w, gbase + ak, 64);
+                const int lok = __shfl(lo, gbase + ak, 64), hik = __shfl(hi, gbase + ak, 64);
+                if (has) {
+                    const uint32_t* src = M32 + (size_t)vk * (size_t)Jw;
+#pragma unroll
+                    for (int i = 0; i < DPLG; ++i) {
+                        const int idx = lig + GS * i;
+                        if (idx < Jw && 4 * idx + 3 >= lok && 4 * idx < hik) {
+                            const uint32_t val =
+                                src[idx] & live_mask4(*reinterpret_cast<const uint4*>(&sX[4 * idx]), hk, wk);
+                            const uint32_t cur = rowW[idx];
+                            const uint32_t want = bytemax4(cur, val);
+                            if (want != cur) {
+                                rowW[idx] = want;
+                                atomicOr(&dirty[idx >> 5], 1u << (idx & 31));
+                            }
+                        }
+                    }
+                    if (STATS && lig == 0) c_sectors += (unsigned long long)(((hik - 1) >> 6) - (lok >> 6) + 1);
+                }
+            }
+
+            // sparse arcs: flattened (arc, word) items within the group
+            const int incl = group_incl_scan<GS>(nd, lig);
+            const int total = __shfl(incl, gbase + GS - 1, 64);
+            const int maxtot = wave_max_i32(total);
+            if (maxtot == 0) continue;
+            ev[lig] = v;
+            eh[lig] = h;
+            eW[lig] = w;
+            edl[lig] = lo >> 2;
+            est[lig] = incl - nd;
+            if (STATS) esec[lig] = 0ull;
+            wave_lds_sync();
+            for (int r = 0; r < maxtot; r += GS) {
+                const int idx = r + lig;
+                uint32_t val = 0u;
+                int d = 0;
                 if (idx < total) {
-                    const int k = owner_of(est, idx);
-                    const int j = elo[k] + (idx - est[k]);
-                    if ((sX[j] ^ eh[k]) < eW[k]) {
-                        uint32_t val = a.M[(size_t)ev[k] * (size_t)J + (size_t)j];
-                        atomicMax(&row[j], val);
+                    const int k = group_owner<GS>(est, idx);
+                    d = edl[k] + (idx - est[k]);
+                    const uint32_t m = live_mask4(*reinterpret_cast<const uint4*>(&sX[4 * d]), eh[k], eW[k]);
+                    if (m) {
+                        val = M32[(size_t)ev[k] * (size_t)Jw + (size_t)d] & m;
+                        if (STATS) atomicOr(&esec[k], 1ull << ((4 * d) >> 6));
                     }
                 }
+                lds_merge_word(&rowW[d], dirty, d, val, val != 0u);
+            }
+            if (STATS) {
+                c_sectors += (unsigned long long)__popcll(esec[lig]);
             }
             wave_lds_sync();
         }
 
+        wave_lds_sync();
+        // store changed words of u's row
+        bool changed = false;
         if (init) {
-            bool changed = false;
+            uint32_t* Mu = MW + (size_t)u * (size_t)Jw;
 #pragma unroll
-            for (int i = 0; i < DPL; ++i) {
-                const int idx = lane + 64 * i;
-                if (idx < Jw) {
-                    uint4 w4 = *reinterpret_cast<const uint4*>(&row[4 * idx]);
-                    uint32_t nwd = w4.x | (w4.y << 8) | (w4.z << 16) | (w4.w << 24);
-                    if (nwd != saved[i]) {
-                        uint32_t* addr = reinterpret_cast<uint32_t*>(Mu) + idx;
-                        if (!split) {
-                            *addr = nwd;
-                            changed = true;
-                        } else {
-                            uint32_t cur = __hip_atomic_load(addr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            for (;;) {
-                                uint32_t want = bytemax4(cur, nwd);
-                                if (want == cur) break;
-                                uint32_t prev = atomicCAS(addr, cur, want);
-                                if (prev == cur) {
-                                    changed = true;
-                                    break;
-                                }
-                                cur = prev;
+            for (int i = 0; i < DPLG; ++i) {
+                const int idx = lig + GS * i;
+                if (idx < Jw && ((dirty[idx >> 5] >> (idx & 31)) & 1u)) {
+                    const uint32_t nwd = rowW[idx];
+                    if (!split) {
+                        Mu[idx] = nwd;
+                        changed = true;
+                        if (STATS) c_wbytes += 4;
+                    } else {
+                        uint32_t cur = Mu[idx];
+                        for (;;) {
+                            const uint32_t want = bytemax4(cur, nwd);
+                            if (want == cur) break;
+                            const uint32_t prev = atomicCAS(&Mu[idx], cur, want);
+                            if (prev == cur) {
+                                changed = true;
+                                if (STATS) c_wbytes += 4;
+                                break;
                             }
+                            cur = prev;
                         }
                     }
                 }
             }
-            const unsigned long long bal = __ballot(changed);
-            if (bal != 0ull && lane == 0) {
-                atomicOr(&a.chg_next[(uint32_t)u >> 5], 1u << (u & 31));
-                atomicAdd(a.changed, 1ull);
+        }
+        const bool gchanged = (__ballot(changed) & gmask) != 0ull;
+        // flag u once per sweep; the first flagger activates u's pullers
+        bool first = false;
+        if (gchanged && lig == 0) {
+            const uint32_t bit = 1u << (u & 31);
+            first = !(atomicOr(&a.chg_next[(uint32_t)u >> 5], bit) & bit);
+        }
+        first = __shfl(first ? 1 : 0, gbase, 64) != 0;
+        int64_t ib = 0, ie = 0;
+        if (first) {
+            if (lig == 0) ++c_changed;
+            ib = g.in_rowptr[u];
+            ie = g.in_rowptr[u + 1];
+        }
+        // few in-arcs: activate the pullers here; else queue u's in-tasks for k_mark
+        const bool direct = first && (ie - ib) <= kDirectMark;
+        int n_in = 0, i_first = 0;
+        if (first && !direct && lig == 0) {
+            i_first = g.in_task_start[u];
+            n_in = g.in_task_start[u + 1] - i_first;
+        }
+        wl_append_ranges(chl, n_in, i_first);
+        const int dch = direct ? (int)((ie - ib + GS - 1) / GS) : 0;
+        const int maxdch = wave_max_i32(dch);
+        for (int c = 0; c < maxdch; ++c) {
+            const int64_t e = ib + (int64_t)c * GS + lig;
+            int cnt = 0;
+            int32_t tf = 0;
+            if (direct && e < ie) {
+                const int32_t wsrc = g.in_col[e];
+                const uint32_t bit = 1u << (wsrc & 31);
+                if (!(atomicOr(&a.act_bm[(uint32_t)wsrc >> 5], bit) & bit)) {
+                    tf = g.task_start[wsrc];
+                    cnt = g.task_start[wsrc + 1] - tf;
+                }
             }
-            wave_lds_sync();
+            wl_append_ranges(act, cnt, tf);
+        }
+    }
+    wl_flush(chl);
+    wl_flush(act);
+    {
+        const unsigned long long tot = wave_sum_u64(c_changed);
+        if (lane == 0 && tot) atomicAdd(a.rows_changed, tot);
+    }
+    if (STATS) {
+        c_wbytes = wave_sum_u64(c_wbytes);
+        c_tasks = wave_sum_u64(c_tasks);
+        c_rows = wave_sum_u64(c_rows);
+        c_scanned = wave_sum_u64(c_scanned);
+        c_active = wave_sum_u64(c_active);
+        c_sectors = wave_sum_u64(c_sectors);
+        if (lane == 0) {
+            atomicAdd(&a.stats->tasks, c_tasks);
+            atomicAdd(&a.stats->rows_read, c_rows);
+            atomicAdd(&a.stats->bytes_written, c_wbytes);
+            atomicAdd(&a.stats->arcs_scanned, c_scanned);
+            atomicAdd(&a.stats->arcs_active, c_active);
+            atomicAdd(&a.stats->sectors, c_sectors);
         }
     }
 }
 
-template <int DPL>
+static int cu_count()
+{
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (cus < 1) cus = 1;
+    }
+    return cus;
+}
+
+template <int GS, int DPLG, bool STATS>
 static hipError_t launch_propagate_t(const PropArgs& a, hipStream_t st)
 {
-    static int grid = 0;
-    const size_t lds = sizeof(uint32_t) * ((size_t)a.J + (size_t)kWaves * ((size_t)a.J + kEdgeBufWords));
-    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_propagate<DPL>),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (err != hipSuccess) return err;
-    int per_cu = 0;
-    err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_propagate<DPL>, kWG, lds);
-    if (err != hipSuccess) return err;
-    int dev = 0, cus = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (per_cu < 1) per_cu = 1;
-    grid = cus * per_cu;
-    int64_t need = (a.g.ntasks + kWaves - 1) / kWaves;
-    if (need < grid) grid = (int)(need > 0 ? need : 1);
-    hipLaunchKernelGGL(k_propagate<DPL>, dim3(grid), dim3(kWG), lds, st, a);
+    constexpr int NG = 64 / GS;
+    const size_t lds = sizeof(uint32_t) * ((size_t)a.J + (size_t)kWaves * 2 * kPropBufCap +
+                                           (size_t)kWaves * NG * ((size_t)(a.J / 4) + group_buf_words<GS, STATS>()));
+    static size_t lds_set = 0;
+    static int per_cu = 0;
+    if (lds_set != lds) {
+        hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_propagate<GS, DPLG, STATS>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (err != hipSuccess) return err;
+        err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_propagate<GS, DPLG, STATS>, kWG, lds);
+        if (err != hipSuccess) return err;
+        if (per_cu < 1) per_cu = 1;
+        lds_set = lds;
+    }
+    int grid = cu_count() * per_cu;
+    if (!a.tasks) {
+        const int64_t need = (a.g.ntasks + kWaves * NG - 1) / (kWaves * NG);
+        if (need < grid) grid = (int)(need > 0 ? need : 1);
+    }
+    hipLaunchKernelGGL((k_propagate<GS, DPLG, STATS>), dim3(grid), dim3(kWG), lds, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_propagate(const GraphDev& g, const uint32_t* X, int J, uint8_t* M, const uint32_t* chg_prev,
-                            uint32_t* chg_next, unsigned long long* changed, hipStream_t st)
+template <int GS, bool STATS>
+static hipError_t launch_propagate_g(const PropArgs& a, hipStream_t st)
 {
-    PropArgs a{g, X, J, M, chg_prev, chg_next, changed};
+    const int dpl = (a.J / 4 + GS - 1) / GS;  // 32-bit words per lane
+    if (dpl <= 1) return launch_propagate_t<GS, 1, STATS>(a, st);
+    if (dpl <= 2) return launch_propagate_t<GS, 2, STATS>(a, st);
+    if (dpl <= 4) return launch_propagate_t<GS, 4, STATS>(a, st);
+    if (dpl <= 8) return launch_propagate_t<GS, 8, STATS>(a, st);
+    return launch_propagate_t<GS, 16, STATS>(a, st);
+}
+
+// Lane-group size for a row width: the smallest of 16/32/64 lanes that keeps
+// at most 16 words of the row per lane, unless a larger one is requested.
+int propagate_group_size(int J, int requested)
+{
+    int gs = (J <= 1024) ? 16 : (J <= 2048) ? 32 : 64;
+    if (requested == 16 || requested == 32 || requested == 64) gs = requested > gs ? requested : gs;
+    return gs;
+}
+
+template <bool STATS>
+static hipError_t launch_propagate_s(const PropArgs& a, int gs, hipStream_t st)
+{
+    if (gs == 16) return launch_propagate_g<16, STATS>(a, st);
+    if (gs == 32) return launch_propagate_g<32, STATS>(a, st);
+    return launch_propagate_g<64, STATS>(a, st);
+}
+
+hipError_t launch_propagate(const GraphDev& g, const uint32_t* X, int J, uint8_t* M, const SweepDev& s, int sweep,
+                            int group_size, PropCounters* stats, hipStream_t st)
+{
     if (g.ntasks == 0) return hipSuccess;
-    if (J <= 256) return launch_propagate_t<1>(a, st);
-    if (J <= 512) return launch_propagate_t<2>(a, st);
-    if (J <= 1024) return launch_propagate_t<4>(a, st);
-    if (J <= 2048) return launch_propagate_t<8>(a, st);
-    return launch_propagate_t<16>(a, st);
+    PropArgs a{g,
+               X,
+               J,
+               M,
+               sweep == 0 ? nullptr : s.act_tasks[sweep & 1],
+               &s.act_count[sweep & 3],
+               s.chg[sweep & 1],
+               s.chg[(sweep + 1) & 1],
+               s.chg_list,
+               &s.chg_count[sweep & 3],
+               s.act_bm,
+               s.act_tasks[(sweep + 1) & 1],
+               &s.act_count[(sweep + 1) & 3],
+               &s.rows_changed[sweep & 3],
+               stats};
+    const int gs = propagate_group_size(J, group_size);
+    return stats ? launch_propagate_s<true>(a, gs, st) : launch_propagate_s<false>(a, gs, st);
+}
+
+// Before sweep s: clear the bitmap sweep s writes, the activation bitmap and
+// the counters sweep s and its mark step accumulate into.
+__global__ void k_sweep_prep(SweepDev s, int64_t nwords, int sweep)
+{
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t* nxt = s.chg[(sweep + 1) & 1];
+    for (int64_t i = i0; i < nwords; i += (int64_t)gridDim.x * blockDim.x) {
+        nxt[i] = 0u;
+        s.act_bm[i] = 0u;
+    }
+    if (i0 == 0) {
+        s.rows_changed[sweep & 3] = 0ull;
+        s.chg_count[sweep & 3] = 0u;
+        s.act_count[(sweep + 1) & 3] = 0u;
+    }
+}
+
+hipError_t launch_sweep_prep(const SweepDev& s, int64_t n, int sweep, hipStream_t st)
+{
+    const int64_t nwords = (n + 31) / 32;
+    int64_t blocks = (nwords + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_sweep_prep, dim3((unsigned)blocks), dim3(256), 0, st, s, nwords, sweep);
+    return hipGetLastError();
+}
+
+// Mark step of sweep s: every source w of an in-arc of a changed row becomes
+// active for sweep s+1 (once, through the activation bitmap) and its
+// out-tasks are appended to the next active task list.
+__global__ __launch_bounds__(kWG) void k_mark(GraphDev g, SweepDev s, int sweep)
+{
+    __shared__ int32_t wbuf[kWaves][kWaveBufCap];
+    const int lane = lane_id();
+    const uint32_t count = s.chg_count[sweep & 3];
+    WaveList nxt{wbuf[threadIdx.x >> 6], 0, s.act_tasks[(sweep + 1) & 1], &s.act_count[(sweep + 1) & 3]};
+    const int64_t nw = (int64_t)gridDim.x * kWaves;
+    for (int64_t q = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); q < (int64_t)count; q += nw) {
+        const int32_t it = s.chg_list[q];
+        const int32_t v = g.in_task_v[it];
+        const int64_t e0 = g.in_task_e0[it];
+        const int64_t ve = g.in_rowptr[v + 1];
+        const int64_t e1 = (e0 + g.in_split < ve) ? e0 + g.in_split : ve;
+        for (int64_t cb = e0; cb < e1; cb += 64) {
+            const int64_t e = cb + lane;
+            int c = 0;
+            int32_t first = 0;
+            if (e < e1) {
+                const int32_t w = g.in_col[e];
+                const uint32_t bit = 1u << (w & 31);
+                if (!(atomicOr(&s.act_bm[(uint32_t)w >> 5], bit) & bit)) {
+                    first = g.task_start[w];
+                    c = g.task_start[w + 1] - first;
+                }
+            }
+            wl_append_ranges(nxt, c, first);
+        }
+    }
+    wl_flush(nxt);
+}
+
+hipError_t launch_mark(const GraphDev& g, const SweepDev& s, int sweep, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mark, dim3(cu_count() * 4), dim3(kWG), 0, st, g, s, sweep);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -585,15 +1000,16 @@ hipError_t launch_argmax(const uint32_t* Ju, const unsigned long long* Hu, const
 
 // ---------------------------------------------------------------------------
 // a7: covering cascade (Alg. 3), union-frontier BFS over all simulations.
+// Frontier lists hold out-tasks, so a hub's arcs are spread over many waves.
 
 __device__ __forceinline__ uint32_t marker(int t) { return 64u + ((uint32_t)t & 63u); }
 __device__ __forceinline__ bool uncovered(uint32_t b) { return b >= 1u && b <= 33u; }
 
 // Level 0: the pick s becomes a seed and is covered in every simulation where
-// it is not yet covered; s forms frontier Q_1.
-__global__ __launch_bounds__(64) void k_cascade_seed(const int32_t* __restrict__ best, int32_t k, uint8_t* M, int J,
-                                                      uint8_t* is_seed, int32_t* seeds, uint32_t* pickJ,
-                                                      unsigned long long* pickH, const uint32_t* Ju,
+// it is not yet covered; its out-tasks form frontier Q_1.
+__global__ __launch_bounds__(64) void k_cascade_seed(GraphDev g, const int32_t* __restrict__ best, int32_t k,
+                                                      uint8_t* M, int J, uint8_t* is_seed, int32_t* seeds,
+                                                      uint32_t* pickJ, unsigned long long* pickH, const uint32_t* Ju,
                                                       const unsigned long long* Hu, CascadeDev c,
                                                       uint32_t cascade_id, uint32_t level_id1)
 {
@@ -611,18 +1027,16 @@ __global__ __launch_bounds__(64) void k_cascade_seed(const int32_t* __restrict__
     bool any = false;
     const uint32_t mk = marker(0);
     for (int idx = lane; idx < (J >> 2); idx += 64) {
-        uint32_t d = row[idx], o = d;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            uint32_t r = (d >> (8 * b)) & 0xffu;
-            if (uncovered(r)) d = (d & ~(0xffu << (8 * b))) | (mk << (8 * b));
-        }
-        if (d != o) {
-            row[idx] = d;
+        const uint32_t d = row[idx];
+        const uint32_t um = uncovered_mask4(d);
+        if (um) {
+            row[idx] = (d & ~um) | ((mk * 0x01010101u) & um);
             any = true;
         }
     }
-    const unsigned long long bal = __ballot(any);
+    const bool anyw = __ballot(any) != 0ull;
+    const int32_t t0 = g.task_start[s], nt = anyw ? g.task_start[s + 1] - t0 : 0;
+    for (int q = lane; q < nt; q += 64) c.q[1][q] = t0 + q;
     if (lane == 0) {
         is_seed[s] = 1;
         seeds[k] = s;
@@ -631,8 +1045,7 @@ __global__ __launch_bounds__(64) void k_cascade_seed(const int32_t* __restrict__
         c.qsize[0] = 0;
         c.qsize[2] = 0;
         c.qsize[3] = 0;
-        c.qsize[1] = bal ? 1u : 0u;
-        c.q[1][0] = s;
+        c.qsize[1] = (uint32_t)nt;
         c.stamp[s] = level_id1;
         c.touched[0] = s;
         *c.ntouched = 1;
@@ -640,19 +1053,23 @@ __global__ __launch_bounds__(64) void k_cascade_seed(const int32_t* __restrict__
     }
 }
 
-hipError_t launch_cascade_seed(const int32_t* best, int32_t k, uint8_t* M, int J, uint8_t* is_seed, int32_t* seeds,
-                               uint32_t* pickJ, unsigned long long* pickH, const uint32_t* Ju,
-                               const unsigned long long* Hu, const CascadeDev& c, uint32_t cascade_id,
-                               uint32_t level_id1, hipStream_t st)
+hipError_t launch_cascade_seed(const GraphDev& g, const int32_t* best, int32_t k, uint8_t* M, int J,
+                               uint8_t* is_seed, int32_t* seeds, uint32_t* pickJ, unsigned long long* pickH,
+                               const uint32_t* Ju, const unsigned long long* Hu, const CascadeDev& c,
+                               uint32_t cascade_id, uint32_t level_id1, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cascade_seed, dim3(1), dim3(64), 0, st, best, k, M, J, is_seed, seeds, pickJ, pickH, Ju, Hu,
-                       c, cascade_id, level_id1);
+    hipLaunchKernelGGL(k_cascade_seed, dim3(1), dim3(64), 0, st, g, best, k, M, J, is_seed, seeds, pickJ, pickH, Ju,
+                       Hu, c, cascade_id, level_id1);
     return hipGetLastError();
 }
 
-// Level t >= 1: expand every u in Q_t along its live arcs in the simulations
-// where u was covered at level t-1; heads still uncovered there become covered
-// (marker of level t) and join Q_{t+1}.  One wave per frontier vertex.
+// Level t >= 1: each task of Q_t expands its vertex u along its arcs, in the
+// simulations where u was covered at level t-1 (registers holding the level
+// t-1 marker).  Those simulations are listed as the 32-bit words of u's row
+// that contain the marker (ED, ascending); each arc's candidate range selects
+// a contiguous slice of ED, and the (arc, word) items are dealt to lanes.
+// Heads still uncovered where the arc is live get the level-t marker (byte
+// stores) and their out-tasks join Q_{t+1} (once per level, via stamp).
 struct LevelArgs {
     GraphDev g;
     const uint32_t* X;
@@ -664,7 +1081,22 @@ struct LevelArgs {
     uint32_t cascade_id;
 };
 
-constexpr int kLevelBufWords = 6 * 64;
+constexpr int kLevelBufWords = 6 * 64 + 2 * kWaveBufCap;
+
+__device__ __forceinline__ int lower_bound_i32(const int* A, int n, int key)
+{
+    int lo = 0, len = n;
+    while (len > 0) {
+        const int half = len >> 1;
+        if (A[lo + half] < key) {
+            lo += half + 1;
+            len -= half + 1;
+        } else {
+            len = half;
+        }
+    }
+    return lo;
+}
 
 __global__ __launch_bounds__(kWG) void k_cascade_level(LevelArgs a)
 {
@@ -674,14 +1106,15 @@ __global__ __launch_bounds__(kWG) void k_cascade_level(LevelArgs a)
     const int wave = (int)(threadIdx.x >> 6);
     const int lane = lane_id();
     uint32_t* sX = smem;
-    uint32_t* roww = smem + J + wave * (Jw + kLevelBufWords);
-    const uint8_t* rowb = reinterpret_cast<const uint8_t*>(roww);
-    int* ev = reinterpret_cast<int*>(roww + Jw);
-    uint32_t* eh = roww + Jw + 64;
-    uint32_t* eW = roww + Jw + 128;
-    int* elo = reinterpret_cast<int*>(roww + Jw + 192);
-    int* est = reinterpret_cast<int*>(roww + Jw + 256);
-    uint32_t* efl = roww + Jw + 320;
+    uint32_t* roww = smem + J + wave * (2 * Jw + kLevelBufWords);
+    int* ED = reinterpret_cast<int*>(roww + Jw);
+    int* ev = ED + Jw;
+    uint32_t* eh = reinterpret_cast<uint32_t*>(ev + 64);
+    uint32_t* eW = eh + 64;
+    int* epl = reinterpret_cast<int*>(eW + 64);
+    int* est = epl + 64;
+    uint32_t* efl = reinterpret_cast<uint32_t*>(est + 64);
+    int32_t* qbuf = reinterpret_cast<int32_t*>(efl + 64);
 
     if (blockIdx.x == 0 && threadIdx.x == 0) a.c.qsize[(a.t + 2) & 3] = 0;
     for (int i = threadIdx.x; i < J; i += kWG) sX[i] = a.X[i];
@@ -691,29 +1124,51 @@ __global__ __launch_bounds__(kWG) void k_cascade_level(LevelArgs a)
     const int32_t* Q = a.c.q[a.t & 1];
     int32_t* Qn = a.c.q[(a.t + 1) & 1];
     uint32_t* qn_ctr = &a.c.qsize[(a.t + 1) & 3];
-    const uint8_t mk_prev = (uint8_t)marker(a.t - 1);
-    const uint8_t mk_cur = (uint8_t)marker(a.t);
+    WaveList qlist{qbuf, 0, Qn, qn_ctr};
+    WaveList tlist{qbuf + kWaveBufCap, 0, a.c.touched, a.c.ntouched};
+    const uint32_t mk_prev = marker(a.t - 1);
+    const uint32_t mk_cur = marker(a.t);
     const GraphDev& g = a.g;
+    const uint32_t* M32 = reinterpret_cast<const uint32_t*>(a.M);
     const int64_t nw = (int64_t)gridDim.x * kWaves;
 
     for (int64_t i = (int64_t)blockIdx.x * kWaves + wave; i < (int64_t)qn; i += nw) {
-        const int32_t u = Q[i];
-        const uint32_t* Mu = reinterpret_cast<const uint32_t*>(a.M + (size_t)u * (size_t)J);
-        for (int idx = lane; idx < Jw; idx += 64) roww[idx] = Mu[idx];
+        const int32_t t = Q[i];
+        const int32_t u = g.task_u[t];
+        const int64_t e0 = g.task_e0[t];
+        const int64_t re = g.rowptr[u + 1];
+        const int64_t e1 = (e0 + g.split < re) ? e0 + g.split : re;
+        const uint32_t* Mu = M32 + (size_t)u * (size_t)Jw;
+        int nE = 0;
+        for (int base = 0; base < Jw; base += 64) {
+            const int idx = base + lane;
+            uint32_t d = 0;
+            if (idx < Jw) {
+                d = Mu[idx];
+                roww[idx] = d;
+            }
+            const bool has = idx < Jw && eq_mask4(d, mk_prev) != 0u;
+            const unsigned long long bal = __ballot(has);
+            if (has) ED[nE + __popcll(bal & ((1ull << lane) - 1ull))] = idx;
+            nE += __popcll(bal);
+        }
         wave_lds_sync();
-        const int64_t rb = g.rowptr[u], re = g.rowptr[u + 1];
-        for (int64_t cb = rb; cb < re; cb += 64) {
+        if (nE == 0) continue;
+        for (int64_t cb = e0; cb < e1; cb += 64) {
             const int64_t e = cb + lane;
-            int cnt = 0, lo = 0;
+            int cnt = 0, pl = 0;
             int32_t v = 0;
             uint32_t h = 0, w = 0;
-            if (e < re) {
+            if (e < e1) {
                 v = g.col[e];
                 w = g.W[e];
                 h = arc_hash((uint32_t)u, (uint32_t)v);
-                int hi;
+                int lo, hi;
                 candidate_range(sX, J, h, w, lo, hi);
-                cnt = hi - lo;
+                if (hi > lo) {
+                    pl = lower_bound_i32(ED, nE, lo >> 2);
+                    cnt = lower_bound_i32(ED, nE, ((hi - 1) >> 2) + 1) - pl;
+                }
             }
             const int incl = wave_incl_scan(cnt);
             const int total = __shfl(incl, 63, 64);
@@ -721,7 +1176,7 @@ __global__ __launch_bounds__(kWG) void k_cascade_level(LevelArgs a)
             ev[lane] = v;
             eh[lane] = h;
             eW[lane] = w;
-            elo[lane] = lo;
+            epl[lane] = pl;
             est[lane] = incl - cnt;
             efl[lane] = 0u;
             wave_lds_sync();
@@ -729,45 +1184,59 @@ __global__ __launch_bounds__(kWG) void k_cascade_level(LevelArgs a)
                 const int idx = r + lane;
                 if (idx < total) {
                     const int k = owner_of(est, idx);
-                    const int j = elo[k] + (idx - est[k]);
-                    if (rowb[j] == mk_prev && (sX[j] ^ eh[k]) < eW[k]) {
-                        uint8_t* p = a.M + (size_t)ev[k] * (size_t)J + (size_t)j;
-                        if (uncovered(*p)) {
-                            *p = mk_cur;
+                    const int d = ED[epl[k] + (idx - est[k])];
+                    uint32_t m = eq_mask4(roww[d], mk_prev) &
+                                 live_mask4(*reinterpret_cast<const uint4*>(&sX[4 * d]), eh[k], eW[k]);
+                    if (m) {
+                        const size_t off = (size_t)ev[k] * (size_t)Jw + (size_t)d;
+                        m &= uncovered_mask4(M32[off]);
+                        if (m) {
+                            uint8_t* p = a.M + off * 4;
+#pragma unroll
+                            for (int b = 0; b < 4; ++b)
+                                if ((m >> (8 * b)) & 1u) p[b] = (uint8_t)mk_cur;
                             efl[k] = 1u;
                         }
                     }
                 }
             }
             wave_lds_sync();
-            bool push_q = false, push_t = false;
+            bool push_t = false;
+            int c = 0;
+            int32_t first = 0;
             if (efl[lane]) {
-                push_q = atomicMax(&a.c.stamp[v], a.level_id) < a.level_id;
+                if (atomicMax(&a.c.stamp[v], a.level_id) < a.level_id) {
+                    first = g.task_start[v];
+                    c = g.task_start[v + 1] - first;
+                }
                 push_t = atomicMax(&a.c.touch_stamp[v], a.cascade_id) < a.cascade_id;
             }
-            wave_append(push_q, v, Qn, qn_ctr);
-            wave_append(push_t, v, a.c.touched, a.c.ntouched);
+            wl_append_ranges(qlist, c, first);
+            wl_append_ranges(tlist, push_t ? 1 : 0, v);
             wave_lds_sync();
         }
     }
+    wl_flush(qlist);
+    wl_flush(tlist);
 }
 
 hipError_t launch_cascade_level(const GraphDev& g, const uint32_t* X, int J, uint8_t* M, const CascadeDev& c, int t,
                                 uint32_t level_id, uint32_t cascade_id, hipStream_t st)
 {
-    static int grid = 0;
     LevelArgs a{g, X, J, M, c, t, level_id, cascade_id};
-    const size_t lds = sizeof(uint32_t) * ((size_t)J + (size_t)kWaves * ((size_t)(J / 4) + kLevelBufWords));
-    if (grid == 0) {
+    const size_t lds = sizeof(uint32_t) * ((size_t)J + (size_t)kWaves * ((size_t)(J / 2) + kLevelBufWords));
+    static size_t lds_set = 0;
+    static int per_cu = 0;
+    if (lds_set != lds) {
         hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cascade_level),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (err != hipSuccess) return err;
-        int dev = 0, cus = 0;
-        (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        grid = cus * 4;
+        err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cascade_level, kWG, lds);
+        if (err != hipSuccess) return err;
+        if (per_cu < 1) per_cu = 1;
+        lds_set = lds;
     }
-    hipLaunchKernelGGL(k_cascade_level, dim3(grid), dim3(kWG), lds, st, a);
+    hipLaunchKernelGGL(k_cascade_level, dim3(cu_count() * per_cu), dim3(kWG), lds, st, a);
     return hipGetLastError();
 }
 
@@ -780,16 +1249,18 @@ __global__ __launch_bounds__(kWG) void k_cascade_finalize(uint8_t* M, int J, uin
     const int Jw = J >> 2;
     const uint32_t nt = *c.ntouched;
     const int64_t nw = (int64_t)gridDim.x * kWaves;
+    unsigned long long dT = 0;
     for (int64_t i = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); i < (int64_t)nt; i += nw) {
         const int32_t v = c.touched[i];
         uint32_t* row = reinterpret_cast<uint32_t*>(M + (size_t)v * (size_t)J);
         uint32_t cnt = 0;
         unsigned long long h = 0;
         for (int idx = lane; idx < Jw; idx += 64) {
-            uint32_t d = row[idx], o = d;
+            uint32_t d = row[idx];
+            const uint32_t o = d;
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                uint32_t r = (d >> (8 * b)) & 0xffu;
+                const uint32_t r = (d >> (8 * b)) & 0xffu;
                 if (r >= 64u) {
                     d &= ~(0xffu << (8 * b));
                 } else if (r) {
@@ -802,25 +1273,19 @@ __global__ __launch_bounds__(kWG) void k_cascade_finalize(uint8_t* M, int J, uin
         cnt = wave_sum_u32(cnt);
         h = wave_sum_u64(h);
         if (lane == 0) {
-            uint32_t old = Ju[v];
+            const uint32_t old = Ju[v];
             Ju[v] = cnt;
             Hu[v] = h;
-            atomicAdd(c.T, (unsigned long long)(old - cnt));
+            dT += (unsigned long long)(old - cnt);
         }
     }
+    if (lane == 0 && dT) atomicAdd(c.T, dT);
 }
 
 hipError_t launch_cascade_finalize(uint8_t* M, int J, uint32_t* Ju, unsigned long long* Hu, const CascadeDev& c,
                                    hipStream_t st)
 {
-    static int grid = 0;
-    if (grid == 0) {
-        int dev = 0, cus = 0;
-        (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        grid = cus * 4;
-    }
-    hipLaunchKernelGGL(k_cascade_finalize, dim3(grid), dim3(kWG), 0, st, M, J, Ju, Hu, c);
+    hipLaunchKernelGGL(k_cascade_finalize, dim3(cu_count() * 8), dim3(kWG), 0, st, M, J, Ju, Hu, c);
     return hipGetLastError();
 }
 

@@ -198,3 +198,45 @@ def test_rmat20_wc_full_size_sampled(imx, orc):
     for j in rng.integers(0, J, 6):
         cov = lg.cover_from(int(X[j]), r["seeds"])
         assert np.array_equal(zeros[:, j], cov.astype(bool)), j
+
+
+@pytest.mark.skipif(os.environ.get("IMX_FULL_RMAT24") != "1",
+                    reason="RMAT-24 (16 GiB of registers, minutes of input generation) runs only when "
+                           "IMX_FULL_RMAT24=1")
+@pytest.mark.parametrize("scheme", ["0.01", "trivalency"])
+def test_rmat24_full_size_sampled(imx, orc, scheme):
+    """RMAT scale 24, J=1024: sampled registers against closed-form
+    reachability, every estimate term of sampled rows, first pick, and the
+    covered sets of sampled simulations after K=50 picks."""
+    g = graphgen.with_p(graphgen.rmat(24, 16, seed=1), scheme)
+    J, seed, K = 1024, 1, 50
+    _say(f"[c3 {scheme}] n={g.n} m={g.m}")
+    G = imx.Graph.from_graphgen(g)
+    S = imx.Sketch(G, J, seed)
+    X = S.sim_values()
+    assert np.array_equal(X, orc.sim_values(seed, J))
+    lg = orc.LiveGraph(g)
+    rng = np.random.default_rng(1)
+    hubs = np.argsort(g.out_degree())[-16:]
+    us = np.concatenate([rng.integers(0, g.n, 120), hubs]).astype(np.int32)
+    rows = S.register_rows(us)
+    Ju0, Hu0 = S.estimates()
+    for i, u in enumerate(us):
+        for j in rng.integers(0, J, 4):
+            assert rows[i, j] == lg.reach_max(int(X[j]), seed, int(j), int(u)), (u, j)
+    Ju_s, Hu_s = orc.estimates(rows)
+    assert np.array_equal(Ju0[us], Ju_s) and np.array_equal(Hu0[us], Hu_s)
+    s0 = orc.argmax(Ju0, Hu0)
+    r = S.select(K)
+    assert r["seeds"][0] == s0
+    assert len(set(r["seeds"].tolist())) == K
+    for j in rng.integers(0, J, 3):
+        cov = lg.cover_from(int(X[j]), r["seeds"]).astype(bool)
+        covered_ids = np.flatnonzero(cov)
+        free_ids = np.flatnonzero(~cov)
+        pick_c = rng.choice(covered_ids, min(2000, covered_ids.size), replace=False).astype(np.int32)
+        pick_f = rng.choice(free_ids, 2000, replace=False).astype(np.int32)
+        assert np.all(S.register_rows(pick_c)[:, j] == 0), j
+        assert np.all(S.register_rows(pick_f)[:, j] != 0), j
+    S.free()
+    G.free()
