@@ -65,7 +65,7 @@ int default_split()
 int group_size_for(int sweep)
 {
     const char* s = std::getenv(sweep == 0 ? "IMX_GROUP_FIRST" : "IMX_GROUP");
-    const int dflt = sweep == 0 ? 64 : 16;
+    const int dflt = 64;
     return s ? std::atoi(s) : dflt;
 }
 
@@ -402,10 +402,10 @@ im_status im_sketch_build(const im_graph* g, int32_t J, uint64_t seed, void* str
         return fail(stc, msg);
     };
     Arena& A = s->arena;
-    if (A.alloc(&s->M, nJ) || A.alloc(&s->X, J) || A.alloc(&s->Ju, n) || A.alloc(&s->Hu, n) ||
+    if (A.alloc(&s->M, nJ) || A.alloc(&s->X, (size_t)J + imx::kBuckets + 1) || A.alloc(&s->Ju, n) || A.alloc(&s->Hu, n) ||
         A.alloc(&s->sw.chg[0], bm_words) || A.alloc(&s->sw.chg[1], bm_words) || A.alloc(&s->sw.act_bm, bm_words) ||
         A.alloc(&s->sw.act_tasks[0], nt) || A.alloc(&s->sw.act_tasks[1], nt) || A.alloc(&s->sw.act_count, 4) ||
-        A.alloc(&s->sw.chg_list, nit) || A.alloc(&s->sw.chg_count, 4) || A.alloc(&s->sw.rows_changed, 4) ||
+        A.alloc(&s->sw.chg_list, nit) || A.alloc(&s->sw.chg_count, 4) || A.alloc(&s->sw.rows_changed, 4) || A.alloc(&s->sw.dense, 4) ||
         A.alloc(&s->is_seed, n) || A.alloc(&s->best, 1) || A.alloc(&s->casc.q[0], nt) || A.alloc(&s->casc.q[1], nt) ||
         A.alloc(&s->casc.qsize, 4) || A.alloc(&s->casc.stamp, n) || A.alloc(&s->casc.touched, n) ||
         A.alloc(&s->casc.ntouched, 1) || A.alloc(&s->casc.touch_stamp, n) || A.alloc(&s->casc.T, 1) ||

@@ -11,6 +11,11 @@ constexpr int kWaves = 4;             // waves per workgroup in the wave-per-tas
 constexpr int kWG = 64 * kWaves;      // workgroup size
 constexpr int kMaxJ = 4096;           // registers per vertex, upper bound
 constexpr int kArgmaxBlocks = 1024;   // partial-argmax workgroups
+constexpr int kBuckets = 1024;        // bucket table over the top bits of the 31-bit X values
+constexpr int kBucketShift = 21;      // X >> 21 selects the bucket
+// LDS words of the X values plus bucket table, padded to 16 bytes so that the
+// per-wave and per-group areas after it keep 8- and 16-byte alignment.
+constexpr int kTableWords = ((kBuckets + 1 + 3) / 4) * 4;
 
 // Device view of a loaded graph and its work decomposition.
 //   Out-tasks: every vertex u with out-degree > 0 owns the tasks
@@ -51,6 +56,7 @@ struct SweepDev {
     int32_t* chg_list;                // [n_in_tasks]
     uint32_t* chg_count;              // [4]
     unsigned long long* rows_changed; // [4]
+    uint32_t* dense;                  // [4] sweep s visits every task when dense[s&3] != 0
 };
 
 // Device state of the covering cascade (union-frontier BFS over tasks).
@@ -81,6 +87,7 @@ struct ArgmaxScratch {
 };
 
 hipError_t launch_thresholds(const float* p, uint32_t* W, int64_t m, hipStream_t st);
+// X holds J sorted values followed by the kBuckets+1 entry bucket table.
 hipError_t launch_sim_values(uint64_t seed, int J, uint32_t* X, hipStream_t st);
 hipError_t launch_fill(uint8_t* M, int64_t n, int J, uint64_t seed, bool first, hipStream_t st);
 hipError_t launch_sweep_prep(const SweepDev& s, int64_t n, int sweep, hipStream_t st);

@@ -113,8 +113,12 @@ __device__ __forceinline__ int lower_bound_lds(const uint32_t* X, int J, uint32_
 
 // Candidate simulations of an arc with hash h and threshold W: since X is
 // sorted and (X xor h) < W <= 2^b forces X >> b == h >> b, every live
-// simulation lies in one contiguous index range [lo, hi) of X.
-__device__ __forceinline__ void candidate_range(const uint32_t* X, int J, uint32_t h, uint32_t W, int& lo, int& hi)
+// simulation lies in one contiguous index range [lo, hi) of X.  T is the
+// bucket table T[k] = first index with X >= k * 2^21 (k = 0..1024): range ends
+// that are multiples of 2^21 are exact lookups, others step through one
+// bucket (about J/1024 entries).
+__device__ __forceinline__ void candidate_range(const uint32_t* X, const uint32_t* T, int J, uint32_t h, uint32_t W,
+                                                int& lo, int& hi)
 {
     if (W == 0u) {
         lo = hi = 0;
@@ -122,10 +126,19 @@ __device__ __forceinline__ void candidate_range(const uint32_t* X, int J, uint32
         lo = 0;
         hi = J;
     } else {
-        int b = (W == 1u) ? 0 : 32 - __builtin_clz(W - 1u);
-        uint32_t base = (h >> b) << b;
-        lo = lower_bound_lds(X, J, base);
-        hi = lower_bound_lds(X, J, base + (1u << b));
+        const int b = (W == 1u) ? 0 : 32 - __builtin_clz(W - 1u);
+        const uint32_t base = (h >> b) << b;
+        const uint32_t top = base + (1u << b);
+        if (b >= kBucketShift) {
+            lo = (int)T[base >> kBucketShift];
+            hi = (int)T[top >> kBucketShift];
+        } else {
+            lo = (int)T[base >> kBucketShift];
+            const int end = (int)T[(base >> kBucketShift) + 1];
+            while (lo < end && X[lo] < base) ++lo;
+            hi = lo;
+            while (hi < end && X[hi] < top) ++hi;
+        }
     }
 }
 
@@ -305,6 +318,8 @@ __global__ __launch_bounds__(1024) void k_sim_values(uint64_t seed, int J, uint3
         }
     }
     for (int i = threadIdx.x; i < J; i += blockDim.x) X[i] = s[i];
+    for (int k = threadIdx.x; k <= kBuckets; k += blockDim.x)
+        X[J + k] = (uint32_t)lower_bound_lds(s, J, (uint32_t)k << kBucketShift);
 }
 
 hipError_t launch_sim_values(uint64_t seed, int J, uint32_t* X, hipStream_t st)
@@ -365,9 +380,9 @@ hipError_t launch_fill(uint8_t* M, int64_t n, int J, uint64_t seed, bool first, 
 //     last writer among colliding lanes exits each round, so it terminates);
 //   - changed words (tracked in a per-group dirty bitmap) are stored to HBM;
 //     rows split over several tasks merge with a byte-max compare-and-swap.
-//     A changed row u is flagged in the next changed bitmap, and the vertices
-//     that pull from u are activated for the next sweep: directly by the group
-//     when u has few in-arcs, otherwise through u's in-tasks and k_mark.
+//     A changed row u is flagged in the next changed bitmap and its in-tasks
+//     are queued; k_mark turns them into the next sweep's active task list,
+//     unless so many rows changed that the next sweep visits every task.
 
 struct PropArgs {
     GraphDev g;
@@ -380,15 +395,12 @@ struct PropArgs {
     uint32_t* chg_next;
     int32_t* chg_list;
     uint32_t* chg_count;
-    uint32_t* act_bm;
-    int32_t* act_next;
-    uint32_t* act_next_count;
+    const uint32_t* dense;        // nonzero: visit every task this sweep
     unsigned long long* rows_changed;
     PropCounters* stats;          // instrumented variant only
 };
 
-constexpr int kDirectMark = 64;   // in-degree up to which a changed row activates its pullers itself
-constexpr int kPropBufCap = 128;  // staging entries per wave and list
+constexpr int kPropBufCap = 256;  // staging entries per wave for the changed in-task list
 
 // LDS words per group besides the row: arc arrays (5 x GS), dirty bitmap
 // (Jw/32 <= 32 words), and (instrumented variant) sector masks (2 x GS).
@@ -470,8 +482,10 @@ __global__ __launch_bounds__(kWG) void k_propagate(PropArgs a)
     const unsigned long long gmask = group_mask(gbase, GS);
 
     uint32_t* sX = smem;
-    int32_t* wbuf = reinterpret_cast<int32_t*>(smem + J + wave * 2 * kPropBufCap);
-    uint32_t* gbuf = smem + J + kWaves * 2 * kPropBufCap + (wave * NG + gi) * (Jw + GB);
+    const uint32_t* sT = smem + J;
+    const int XT = J + kTableWords;
+    int32_t* wbuf = reinterpret_cast<int32_t*>(smem + XT + wave * kPropBufCap);
+    uint32_t* gbuf = smem + XT + kWaves * kPropBufCap + (wave * NG + gi) * (Jw + GB);
     uint32_t* rowW = gbuf;  // Jw words = J register bytes
     int* ev = reinterpret_cast<int*>(gbuf + Jw);
     uint32_t* eh = gbuf + Jw + GS;
@@ -481,17 +495,19 @@ __global__ __launch_bounds__(kWG) void k_propagate(PropArgs a)
     uint32_t* dirty = gbuf + Jw + 5 * GS;
     unsigned long long* esec = reinterpret_cast<unsigned long long*>(gbuf + Jw + 5 * GS + 32);  // STATS only
     WaveList chl{wbuf, 0, a.chg_list, a.chg_count, kPropBufCap};
-    WaveList act{wbuf + kPropBufCap, 0, a.act_next, a.act_next_count, kPropBufCap};
     unsigned long long c_tasks = 0, c_rows = 0, c_wbytes = 0, c_scanned = 0, c_active = 0, c_sectors = 0;
     unsigned long long c_changed = 0;
 
-    for (int i = threadIdx.x; i < J; i += kWG) sX[i] = a.X[i];
+    for (int i = threadIdx.x; i < J + kBuckets + 1; i += kWG) sX[i] = a.X[i];
     __syncthreads();
 
     const GraphDev& g = a.g;
     const uint32_t* M32 = reinterpret_cast<const uint32_t*>(a.M);
     uint32_t* MW = reinterpret_cast<uint32_t*>(a.M);
-    const int64_t count = a.tasks ? (int64_t)*a.task_count : g.ntasks;
+    // every task after a fill or after a sweep that changed many rows; else the active list
+    const bool all = a.tasks == nullptr || *a.dense != 0u;
+    const int32_t* tasks = all ? nullptr : a.tasks;
+    const int64_t count = all ? g.ntasks : (int64_t)*a.task_count;
     const int64_t ngroups = (int64_t)gridDim.x * kWaves * NG;
 
     for (int64_t qb = ((int64_t)blockIdx.x * kWaves + wave) * NG; qb < count; qb += ngroups) {
@@ -501,7 +517,7 @@ __global__ __launch_bounds__(kWG) void k_propagate(PropArgs a)
         int64_t e0 = 0, e1 = 0;
         bool split = false;
         if (valid) {
-            const int32_t t = a.tasks ? a.tasks[q] : (int32_t)q;
+            const int32_t t = tasks ? tasks[q] : (int32_t)q;
             u = g.task_u[t];
             e0 = g.task_e0[t];
             const uint32_t len = g.task_len[t];
@@ -511,7 +527,18 @@ __global__ __launch_bounds__(kWG) void k_propagate(PropArgs a)
         if (STATS && valid && lig == 0) ++c_tasks;
         const int nch = valid ? (int)((e1 - e0 + GS - 1) / GS) : 0;
         const int maxch = wave_max_i32(nch);
-        bool init = false;  // group-uniform
+        // stage u's row in LDS and clear the dirty bitmap
+        if (valid) {
+            const uint32_t* Mu = M32 + (size_t)u * (size_t)Jw;
+#pragma unroll
+            for (int i = 0; i < DPLG; ++i) {
+                const int idx = lig + GS * i;
+                if (idx < Jw) rowW[idx] = Mu[idx];
+            }
+            if (lig < 32) dirty[lig] = 0u;
+            if (GS == 16) dirty[lig + 16] = 0u;
+        }
+        bool touched = false;  // group-uniform: some arc had candidates
         for (int c = 0; c < maxch; ++c) {
             const int64_t e = e0 + (int64_t)c * GS + lig;
             int cnt = 0, lo = 0, hi = 0;
@@ -524,7 +551,7 @@ __global__ __launch_bounds__(kWG) void k_propagate(PropArgs a)
                 act_arc = (a.chg_prev[(uint32_t)v >> 5] >> (v & 31)) & 1u;
                 if (act_arc && w != 0u) {
                     h = arc_hash((uint32_t)u, (uint32_t)v);
-                    candidate_range(sX, J, h, w, lo, hi);
+                    candidate_range(sX, sT, J, h, w, lo, hi);
                     cnt = hi - lo;
                 }
             }
@@ -533,17 +560,8 @@ __global__ __launch_bounds__(kWG) void k_propagate(PropArgs a)
                 c_active += act_arc ? 1ull : 0ull;
             }
             const bool gany = (__ballot(cnt > 0) & gmask) != 0ull;
-            if (gany && !init) {
-                // stage u's row in LDS and clear the dirty bitmap
-                const uint32_t* Mu = M32 + (size_t)u * (size_t)Jw;
-#pragma unroll
-                for (int i = 0; i < DPLG; ++i) {
-                    const int idx = lig + GS * i;
-                    if (idx < Jw) rowW[idx] = Mu[idx];
-                }
-                if (lig < 32) dirty[lig] = 0u;
-                if (GS == 16 && lig < 16) dirty[lig + 16] = 0u;
-                init = true;
+            if (gany && !touched) {
+                touched = true;
                 if (STATS && lig == 0) ++c_rows;
             }
             const bool dense = cnt > 0 && 2 * cnt >= J;
@@ -592,20 +610,32 @@ __global__ __launch_bounds__(kWG) void k_propagate(PropArgs a)
             est[lig] = incl - nd;
             if (STATS) esec[lig] = 0ull;
             wave_lds_sync();
-            for (int r = 0; r < maxtot; r += GS) {
-                const int idx = r + lig;
-                uint32_t val = 0u;
-                int d = 0;
-                if (idx < total) {
-                    const int k = group_owner<GS>(est, idx);
-                    d = edl[k] + (idx - est[k]);
-                    const uint32_t m = live_mask4(*reinterpret_cast<const uint4*>(&sX[4 * d]), eh[k], eW[k]);
-                    if (m) {
-                        val = M32[(size_t)ev[k] * (size_t)Jw + (size_t)d] & m;
-                        if (STATS) atomicOr(&esec[k], 1ull << ((4 * d) >> 6));
+            for (int r = 0; r < maxtot; r += 2 * GS) {
+                uint32_t val0 = 0u, val1 = 0u, m0 = 0u, m1 = 0u;
+                int d0 = 0, d1 = 0;
+                const int i0 = r + lig, i1 = r + GS + lig;
+                if (i0 < total) {
+                    const int k = group_owner<GS>(est, i0);
+                    d0 = edl[k] + (i0 - est[k]);
+                    m0 = live_mask4(*reinterpret_cast<const uint4*>(&sX[4 * d0]), eh[k], eW[k]);
+                    if (m0) {
+                        val0 = M32[(size_t)ev[k] * (size_t)Jw + (size_t)d0];
+                        if (STATS) atomicOr(&esec[k], 1ull << ((4 * d0) >> 6));
                     }
                 }
-                lds_merge_word(&rowW[d], dirty, d, val, val != 0u);
+                if (i1 < total) {
+                    const int k = group_owner<GS>(est, i1);
+                    d1 = edl[k] + (i1 - est[k]);
+                    m1 = live_mask4(*reinterpret_cast<const uint4*>(&sX[4 * d1]), eh[k], eW[k]);
+                    if (m1) {
+                        val1 = M32[(size_t)ev[k] * (size_t)Jw + (size_t)d1];
+                        if (STATS) atomicOr(&esec[k], 1ull << ((4 * d1) >> 6));
+                    }
+                }
+                val0 &= m0;
+                val1 &= m1;
+                lds_merge_word(&rowW[d0], dirty, d0, val0, val0 != 0u);
+                lds_merge_word(&rowW[d1], dirty, d1, val1, val1 != 0u);
             }
             if (STATS) {
                 c_sectors += (unsigned long long)__popcll(esec[lig]);
@@ -616,7 +646,7 @@ __global__ __launch_bounds__(kWG) void k_propagate(PropArgs a)
         wave_lds_sync();
         // store changed words of u's row
         bool changed = false;
-        if (init) {
+        if (touched) {
             uint32_t* Mu = MW + (size_t)u * (size_t)Jw;
 #pragma unroll
             for (int i = 0; i < DPLG; ++i) {
@@ -652,39 +682,15 @@ __global__ __launch_bounds__(kWG) void k_propagate(PropArgs a)
             first = !(atomicOr(&a.chg_next[(uint32_t)u >> 5], bit) & bit);
         }
         first = __shfl(first ? 1 : 0, gbase, 64) != 0;
-        int64_t ib = 0, ie = 0;
-        if (first) {
-            if (lig == 0) ++c_changed;
-            ib = g.in_rowptr[u];
-            ie = g.in_rowptr[u + 1];
-        }
-        // few in-arcs: activate the pullers here; else queue u's in-tasks for k_mark
-        const bool direct = first && (ie - ib) <= kDirectMark;
         int n_in = 0, i_first = 0;
-        if (first && !direct && lig == 0) {
+        if (first && lig == 0) {
+            ++c_changed;
             i_first = g.in_task_start[u];
             n_in = g.in_task_start[u + 1] - i_first;
         }
         wl_append_ranges(chl, n_in, i_first);
-        const int dch = direct ? (int)((ie - ib + GS - 1) / GS) : 0;
-        const int maxdch = wave_max_i32(dch);
-        for (int c = 0; c < maxdch; ++c) {
-            const int64_t e = ib + (int64_t)c * GS + lig;
-            int cnt = 0;
-            int32_t tf = 0;
-            if (direct && e < ie) {
-                const int32_t wsrc = g.in_col[e];
-                const uint32_t bit = 1u << (wsrc & 31);
-                if (!(atomicOr(&a.act_bm[(uint32_t)wsrc >> 5], bit) & bit)) {
-                    tf = g.task_start[wsrc];
-                    cnt = g.task_start[wsrc + 1] - tf;
-                }
-            }
-            wl_append_ranges(act, cnt, tf);
-        }
     }
     wl_flush(chl);
-    wl_flush(act);
     {
         const unsigned long long tot = wave_sum_u64(c_changed);
         if (lane == 0 && tot) atomicAdd(a.rows_changed, tot);
@@ -723,7 +729,7 @@ template <int GS, int DPLG, bool STATS>
 static hipError_t launch_propagate_t(const PropArgs& a, hipStream_t st)
 {
     constexpr int NG = 64 / GS;
-    const size_t lds = sizeof(uint32_t) * ((size_t)a.J + (size_t)kWaves * 2 * kPropBufCap +
+    const size_t lds = sizeof(uint32_t) * ((size_t)a.J + kTableWords + (size_t)kWaves * kPropBufCap +
                                            (size_t)kWaves * NG * ((size_t)(a.J / 4) + group_buf_words<GS, STATS>()));
     static size_t lds_set = 0;
     static int per_cu = 0;
@@ -737,10 +743,8 @@ static hipError_t launch_propagate_t(const PropArgs& a, hipStream_t st)
         lds_set = lds;
     }
     int grid = cu_count() * per_cu;
-    if (!a.tasks) {
-        const int64_t need = (a.g.ntasks + kWaves * NG - 1) / (kWaves * NG);
-        if (need < grid) grid = (int)(need > 0 ? need : 1);
-    }
+    const int64_t need = (a.g.ntasks + kWaves * NG - 1) / (kWaves * NG);
+    if (need < grid) grid = (int)(need > 0 ? need : 1);
     hipLaunchKernelGGL((k_propagate<GS, DPLG, STATS>), dim3(grid), dim3(kWG), lds, st, a);
     return hipGetLastError();
 }
@@ -787,9 +791,7 @@ hipError_t launch_propagate(const GraphDev& g, const uint32_t* X, int J, uint8_t
                s.chg[(sweep + 1) & 1],
                s.chg_list,
                &s.chg_count[sweep & 3],
-               s.act_bm,
-               s.act_tasks[(sweep + 1) & 1],
-               &s.act_count[(sweep + 1) & 3],
+               &s.dense[sweep & 3],
                &s.rows_changed[sweep & 3],
                stats};
     const int gs = propagate_group_size(J, group_size);
@@ -823,6 +825,8 @@ hipError_t launch_sweep_prep(const SweepDev& s, int64_t n, int sweep, hipStream_
     return hipGetLastError();
 }
 
+constexpr int kDenseFraction = 16;  // dense next sweep when more than n/16 rows changed
+
 // Mark step of sweep s: every source w of an in-arc of a changed row becomes
 // active for sweep s+1 (once, through the activation bitmap) and its
 // out-tasks are appended to the next active task list.
@@ -830,6 +834,11 @@ __global__ __launch_bounds__(kWG) void k_mark(GraphDev g, SweepDev s, int sweep)
 {
     __shared__ int32_t wbuf[kWaves][kWaveBufCap];
     const int lane = lane_id();
+    // Many changed rows: the next sweep visits every task (with per-arc
+    // changed-head tests) instead of building a list.
+    const bool dense = s.rows_changed[sweep & 3] * (unsigned long long)kDenseFraction > (unsigned long long)g.n;
+    if (blockIdx.x == 0 && threadIdx.x == 0) s.dense[(sweep + 1) & 3] = dense ? 1u : 0u;
+    if (dense) return;
     const uint32_t count = s.chg_count[sweep & 3];
     WaveList nxt{wbuf[threadIdx.x >> 6], 0, s.act_tasks[(sweep + 1) & 1], &s.act_count[(sweep + 1) & 3]};
     const int64_t nw = (int64_t)gridDim.x * kWaves;
@@ -1106,7 +1115,9 @@ __global__ __launch_bounds__(kWG) void k_cascade_level(LevelArgs a)
     const int wave = (int)(threadIdx.x >> 6);
     const int lane = lane_id();
     uint32_t* sX = smem;
-    uint32_t* roww = smem + J + wave * (2 * Jw + kLevelBufWords);
+    const uint32_t* sT = smem + J;
+    const int XT = J + kTableWords;
+    uint32_t* roww = smem + XT + wave * (2 * Jw + kLevelBufWords);
     int* ED = reinterpret_cast<int*>(roww + Jw);
     int* ev = ED + Jw;
     uint32_t* eh = reinterpret_cast<uint32_t*>(ev + 64);
@@ -1117,7 +1128,7 @@ __global__ __launch_bounds__(kWG) void k_cascade_level(LevelArgs a)
     int32_t* qbuf = reinterpret_cast<int32_t*>(efl + 64);
 
     if (blockIdx.x == 0 && threadIdx.x == 0) a.c.qsize[(a.t + 2) & 3] = 0;
-    for (int i = threadIdx.x; i < J; i += kWG) sX[i] = a.X[i];
+    for (int i = threadIdx.x; i < J + kBuckets + 1; i += kWG) sX[i] = a.X[i];
     __syncthreads();
 
     const uint32_t qn = a.c.qsize[a.t & 3];
@@ -1164,7 +1175,7 @@ __global__ __launch_bounds__(kWG) void k_cascade_level(LevelArgs a)
                 w = g.W[e];
                 h = arc_hash((uint32_t)u, (uint32_t)v);
                 int lo, hi;
-                candidate_range(sX, J, h, w, lo, hi);
+                candidate_range(sX, sT, J, h, w, lo, hi);
                 if (hi > lo) {
                     pl = lower_bound_i32(ED, nE, lo >> 2);
                     cnt = lower_bound_i32(ED, nE, ((hi - 1) >> 2) + 1) - pl;
@@ -1224,7 +1235,8 @@ hipError_t launch_cascade_level(const GraphDev& g, const uint32_t* X, int J, uin
                                 uint32_t level_id, uint32_t cascade_id, hipStream_t st)
 {
     LevelArgs a{g, X, J, M, c, t, level_id, cascade_id};
-    const size_t lds = sizeof(uint32_t) * ((size_t)J + (size_t)kWaves * ((size_t)(J / 2) + kLevelBufWords));
+    const size_t lds =
+        sizeof(uint32_t) * ((size_t)J + kTableWords + (size_t)kWaves * ((size_t)(J / 2) + kLevelBufWords));
     static size_t lds_set = 0;
     static int per_cu = 0;
     if (lds_set != lds) {
