@@ -70,6 +70,47 @@ def pmc_traffic(workload: str, launches_bytes_per_launch: float):
     return d.get("hbm_bytes_per_launch")
 
 
+def _counter_rows(path: str, counter: str):
+    """(kernel name, value) per dispatch from a rocprofv3 counter_collection.csv."""
+    import csv
+    out = []
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            if r.get("Counter_Name") == counter:
+                out.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    return out
+
+
+def pmc_summary(args):
+    """HBM bytes per k_propagate launch from FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch), each scaled by the factor that makes the same counter read the
+    known traffic of a plain device copy (read n bytes, write n bytes)."""
+    import numpy as np
+    fetch, write, cfetch, cwrite = args.pmc_summary
+    copy_bytes = args.copy_calibration << 20 if args.copy_calibration else 1 << 30
+
+    def big(rows):  # the copy kernel is the dispatch with the largest count
+        return max(v for _, v in rows)
+
+    f_fetch = copy_bytes / (big(_counter_rows(cfetch, "FETCH_SIZE")) * 1024)
+    f_write = copy_bytes / (big(_counter_rows(cwrite, "WRITE_SIZE")) * 1024)
+    fr = [v for k, v in _counter_rows(fetch, "FETCH_SIZE") if "k_propagate" in k]
+    wr = [v for k, v in _counter_rows(write, "WRITE_SIZE") if "k_propagate" in k]
+    if not fr or not wr:
+        raise SystemExit("no k_propagate dispatches in the counter files")
+    fb = float(np.mean(fr)) * 1024 * f_fetch
+    wb = float(np.mean(wr)) * 1024 * f_write
+    d = {"workload": args.workload, "kernel": "k_propagate", "kernel_source_hash": kernel_source_hash(),
+         "dispatches": [len(fr), len(wr)], "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+         "hbm_bytes_per_launch": fb + wb, "copy_calibration": {"bytes": copy_bytes, "fetch_factor": f_fetch,
+                                                               "write_factor": f_write},
+         "command": args.pmc_command}
+    path = os.path.join(ROOT, "profiles", f"propagate_{args.workload}_pmc.json")
+    with open(path, "w") as f:
+        json.dump(d, f, indent=1)
+    print(json.dumps(d))
+
+
 def cpu_baseline(g, w, budget_s: float):
     """The oracle (single thread, as it stands) running full synchronous sweeps
     over a subset of the J simulation columns of the same graph."""
@@ -91,19 +132,174 @@ def cpu_baseline(g, w, budget_s: float):
                       f"all {g.m} arcs, single thread; {dt:.1f} s"}
 
 
+def batched_main(args):
+    """64 independent graphs of uneven size (32 RMAT, scales 12-18; 32
+    Barabasi-Albert, n 10k-200k, m0=8), weighted cascade, J=256, K=20, sketch
+    seeds 0..63: one engine (batched launches) against one query per launch
+    (sequential one-query engines), with identical outputs required."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_2410_14047_amd as imx
+    from paper_2410_14047_amd import autotune
+
+    rng = np.random.Generator(np.random.PCG64(4))
+    specs = [("rmat", int(rng.integers(12, 19)), i) for i in range(32)]
+    specs += [("ba", int(rng.integers(10_000, 200_001)), i) for i in range(32)]
+    t0 = time.perf_counter()
+    gs = []
+    for kind, size, i in specs:
+        g = graphgen.rmat(size, 16, seed=100 + i) if kind == "rmat" else graphgen.barabasi_albert(size, 8, seed=i)
+        gs.append(graphgen.with_p(g, "wc"))
+    print(f"[bench] 64 graphs, {sum(g.m for g in gs)} arcs ({time.perf_counter() - t0:.1f} s)", file=sys.stderr,
+          flush=True)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    Gs = [imx.Graph.from_graphgen(g, stream=stream) for g in gs]
+    J, K = 256, 20
+    queries = [(G, J, i, K) for i, G in enumerate(Gs)]
+
+    # autotune on every 8th query (not timed)
+    tuned = autotune.autotune(queries[::8], candidates=[
+        dict(group_first=gf, group_rest=gr, rounds_per_step=r, dense_div=16)
+        for gf in (32, 64) for gr in (16, 64) for r in (2, 4)], stream=stream)
+    tuning = tuned["best"]
+    print(f"[bench] tuning {tuning}", file=sys.stderr, flush=True)
+
+    def run_batched():
+        E = imx.Engine(max_queries=64, stream=stream)
+        E.set_tuning(**tuning)
+        ids = [E.submit(*q) for q in queries]
+        res = E.run()
+        E.free()
+        return [res[i] for i in ids]
+
+    def run_single():
+        out = []
+        for (G, J_, s, K_) in queries:
+            S = imx.Sketch(G, J_, s, stream=stream)
+            out.append(S.select(K_))
+            S.free()
+        return out
+
+    run_batched()  # warm-up
+    times = {}
+    for name, fn in (("batched", run_batched), ("one_query_per_launch", run_single)):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res = fn()
+        torch.cuda.synchronize()
+        times[name] = (time.perf_counter() - t, res)
+        print(f"[bench] {name}: {times[name][0]:.3f} s", file=sys.stderr, flush=True)
+    a, b = times["batched"][1], times["one_query_per_launch"][1]
+    for ra, rb in zip(a, b):
+        assert list(ra["seeds"]) == list(rb["seeds"]) and list(ra["T"]) == list(rb["T"]), "outputs differ"
+    upd = sum(J * G.m * r["stats"]["total_sweeps"] for G, r in zip(Gs, a))
+    tb, ts = times["batched"][0], times["one_query_per_launch"][0]
+    print(json.dumps({
+        "metric": "batched IM queries: wall time of 64 queries (and register updates/s)",
+        "value": 64 / tb, "unit": "queries/s", "n_gpus": 1, "higher_is_better": True,
+        "batched_s": tb, "one_query_per_launch_s": ts, "speedup": ts / tb,
+        "register_updates_per_s": upd / tb, "identical_outputs": True, "tuning": tuning,
+        "config": {"workload": "batched64_rmat12-18_ba10k-200k_wc_J256_K20", "graphs": 64,
+                   "arcs": int(sum(g.m for g in gs)), "J": J, "K": K},
+        "data": "synthetic", "dtype": "u8"}), flush=True)
+
+
+def served_main(args):
+    """Poisson stream of IM queries over device-resident graphs (RMAT scales
+    given by --served-scales, edge factor 16, two p-schemes each), J in
+    {128, 512}, K uniform in [10, 100]: continuous batching against a serial
+    one-query-at-a-time server on the same trace."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_2410_14047_amd as imx
+    from paper_2410_14047_amd import serve
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    scales = [int(x) for x in args.served_scales.split(",")]
+    graphs = {}
+    t0 = time.perf_counter()
+    for i, sc in enumerate(scales):
+        base = graphgen.rmat(sc, 16, seed=1 if i < len(scales) - 1 or scales.count(sc) == 1 else 2)
+        for scheme in ("0.01", "wc"):
+            graphs[f"rmat{sc}_{i}_{scheme}"] = imx.Graph.from_graphgen(graphgen.with_p(base, scheme), stream=stream)
+    print(f"[bench] {len(graphs)} resident graphs ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    names = sorted(graphs)
+    rng = np.random.Generator(np.random.PCG64(1))
+    nq = args.served_queries
+    reqs = [(names[int(rng.integers(len(names)))], int(rng.choice([128, 512])), int(i),
+             int(rng.integers(10, 101))) for i in range(nq)]
+
+    def serial_time(sample):
+        t = time.perf_counter()
+        for (gname, J, s, K) in sample:
+            S = imx.Sketch(graphs[gname], J, s, stream=stream)
+            S.select(K)
+            S.free()
+        return (time.perf_counter() - t) / len(sample)
+
+    svc = serial_time(reqs[: max(4, nq // 8)])
+    out = {"metric": "served IM queries: throughput and p50/p99 latency",
+           "unit": "queries/s", "n_gpus": 1, "mean_serial_service_s": svc, "levels": []}
+    for load in [float(x) for x in args.served_loads.split(",")]:
+        lam = load / svc
+        arr = np.cumsum(rng.exponential(1.0 / lam, size=nq))
+        trace = [(float(t), *r) for t, r in zip(arr, reqs)]
+        row = {"load": load, "lambda_qps": lam}
+        for mode, mq in (("continuous_batching", args.served_slots), ("serial", 1)):
+            srv = serve.Server(graphs, max_queries=mq, stream=stream).start()
+            res, span = serve.replay(srv, trace)
+            srv.stop()
+            row[mode] = serve.latency_summary(res, span)
+            row[mode + "_results"] = res
+            print(f"[bench] load {load} {mode}: {row[mode]}", file=sys.stderr, flush=True)
+        a, b = row.pop("continuous_batching_results"), row.pop("serial_results")
+        for ra, rb in zip(a, b):
+            assert list(ra["seeds"]) == list(rb["seeds"]) and list(ra["T"]) == list(rb["T"]), "outputs differ"
+        row["identical_outputs"] = True
+        out["levels"].append(row)
+    out["value"] = max(r["continuous_batching"]["throughput_qps"] for r in out["levels"])
+    out["config"] = {"workload": "served_rmat" + "-".join(map(str, scales)) + "_p0.01+wc_J128|512_K10-100",
+                     "queries_per_level": nq, "slots": args.served_slots}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + ["batched64", "served"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-roofline", action="store_true", help="skip the instrumented byte-count pass")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates rocprofv3 "
                          "FETCH_SIZE / WRITE_SIZE against a kernel of known traffic)")
+    ap.add_argument("--served-scales", default="16,17,18,19,20,21,22,22")
+    ap.add_argument("--served-queries", type=int, default=64)
+    ap.add_argument("--served-loads", default="0.5,0.8,1.0")
+    ap.add_argument("--served-slots", type=int, default=16)
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="turn rocprofv3 counter_collection.csv files of this workload and of the copy "
+                         "calibration into profiles/propagate_<workload>_pmc.json and print it")
+    ap.add_argument("--pmc-command", default="", help="the command line recorded in the --pmc-summary output")
     args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the simulation-column "
+              f"split across GPUs is not built).", file=sys.stderr)
+        sys.exit(2)
+    if args.pmc_summary:
+        return pmc_summary(args)
+    if args.workload == "batched64":
+        return batched_main(args)
+    if args.workload == "served":
+        return served_main(args)
     if args.copy_calibration:
         import torch
         nbytes = args.copy_calibration << 20
@@ -114,10 +310,6 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": nbytes, "launches": 3}), flush=True)
         return
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the method's "
-              f"multi-GPU split is described in DESIGN.md but not built).", file=sys.stderr)
-        sys.exit(2)
 
     import torch
 

@@ -126,13 +126,39 @@ def rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19,
 
 
 def barabasi_albert(n: int, m0: int = 8, seed: int = 0) -> Graph:
-    """Undirected preferential-attachment graph, two arcs per edge."""
-    import networkx as nx
-    gx = nx.barabasi_albert_graph(n, m0, seed=seed)
-    e = np.asarray(gx.edges(), dtype=np.int64).reshape(-1, 2)
-    src = np.concatenate([e[:, 0], e[:, 1]])
-    dst = np.concatenate([e[:, 1], e[:, 0]])
-    g = csr_from_edges(n, src, dst)
+    """Undirected preferential-attachment graph, two arcs per edge.
+
+    Vertex m0 joins vertices 0..m0-1; every later vertex t adds m0 edges whose
+    far ends are uniform picks among the endpoints of all earlier edges, i.e.
+    proportional to degree (the Bollobas-Riordan linearized chord diagram
+    form of the Barabasi-Albert model).  The picks are resolved with pointer
+    jumping, so generation is vectorised.  Repeated picks by one vertex
+    collapse to one edge."""
+    if n <= m0:
+        raise ValueError("n must exceed m0")
+    rng = np.random.Generator(np.random.PCG64(seed))
+    E = m0 + (n - m0 - 1) * m0
+    k = np.arange(E, dtype=np.int64)
+    src = np.empty(E, dtype=np.int64)
+    src[:m0] = m0
+    src[m0:] = m0 + 1 + (k[m0:] - m0) // m0
+    # first edge index of each edge's source vertex: picks come from earlier vertices only
+    k0 = np.where(k < m0, 0, m0 + ((k - m0) // m0) * m0)
+    val = np.full(2 * E, -1, dtype=np.int64)   # endpoint value per position (2k: src, 2k+1: target)
+    val[0::2] = src
+    val[1:2 * m0:2] = np.arange(m0)
+    ptr = np.arange(2 * E, dtype=np.int64)
+    late = np.arange(m0, E)
+    ptr[2 * late + 1] = (rng.random(late.size) * (2 * k0[late])).astype(np.int64)
+    todo = 2 * late + 1
+    while todo.size:
+        q = ptr[todo]
+        got = val[q] >= 0
+        val[todo[got]] = val[q[got]]
+        todo = todo[~got]
+        ptr[todo] = ptr[ptr[todo]]
+    tgt = val[1::2]
+    g = csr_from_edges(n, np.concatenate([src, tgt]), np.concatenate([tgt, src]))
     g.name = f"ba_n{n}_m{m0}_s{seed}"
     return g
 

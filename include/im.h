@@ -171,6 +171,76 @@ im_status im_sketch_sim_values(const im_sketch* s, uint32_t* X_host);
 
 void im_sketch_free(im_sketch* s);
 
+/*
+ * Engines run many queries (graph, J, seed, K) together: every query follows
+ * exactly the steps of im_sketch_build + im_select_seeds, and the engine
+ * advances all of them one stage per im_engine_step, sharing kernel launches
+ * (one batched launch per kernel kind) and one host synchronisation per step.
+ * A query's results do not depend on the other queries in the engine.
+ * Queries may be submitted at any time (continuous admission); a submission
+ * that would exceed the engine's device-memory budget returns IM_ENOMEM and
+ * changes nothing, so the caller can retry after results are collected.
+ *
+ *   max_queries       concurrent queries (slots), 1..4096.
+ *   hbm_budget_bytes  device memory the engine's queries may hold (0: the
+ *                     device's free memory at creation).
+ *   stream            stream of all the engine's work.
+ * Graphs must outlive the engine's queries on them.
+ */
+typedef struct im_engine im_engine;
+
+im_status im_engine_create(int32_t max_queries, uint64_t hbm_budget_bytes, void* stream, im_engine** out);
+
+/* Scheduling parameters of an engine (they change speed, never results):
+ *   group_first, group_rest  lanes per propagation task (16, 32 or 64) in the
+ *                            first sweep after a fill and in later sweeps;
+ *   rounds_per_step          sweeps / cascade levels launched per step (1..4);
+ *   dense_div                a sweep visits every task instead of an active
+ *                            list when more than n / dense_div rows changed in
+ *                            the previous sweep (>= 1).
+ * Defaults: 64, 64, 4, 16 (environment IMX_GROUP_FIRST / IMX_GROUP override
+ * the group sizes). */
+typedef struct im_tuning {
+    int32_t group_first;
+    int32_t group_rest;
+    int32_t rounds_per_step;
+    int32_t dense_div;
+} im_tuning;
+
+im_status im_engine_set_tuning(im_engine* e, const im_tuning* t);
+im_status im_engine_get_tuning(const im_engine* e, im_tuning* t);
+
+/* Admit a query; *query_id receives its id.  Errors: IM_EINVAL (J, K, graph),
+ * IM_ENOMEM (no free slot or budget exceeded; nothing changed), IM_EDEVICE. */
+im_status im_engine_submit(im_engine* e, const im_graph* g, int32_t J, uint64_t seed, int32_t K, int64_t* query_id);
+
+/* Advance every running query by one stage (a few sweeps or cascade levels).
+ * *n_running (optional) receives the number of queries still running. */
+im_status im_engine_step(im_engine* e, int32_t* n_running);
+
+/* Ids of finished queries (up to capacity of them in done_ids; *n_done = all). */
+im_status im_engine_poll(im_engine* e, int64_t* done_ids, int32_t capacity, int32_t* n_done);
+
+/* Results of a finished query (same meaning as im_select_seeds); the query's
+ * device memory is released and its id becomes invalid.  IM_ESTATE if the
+ * query has not finished. */
+im_status im_engine_result(im_engine* e, int64_t query_id, int32_t* seeds_host, double* spread_out,
+                           double* est_host, uint64_t* T_host, im_stats* stats_out);
+
+/* Queries held, queries running, device bytes held and the budget. */
+im_status im_engine_info(const im_engine* e, int32_t* n_queries, int32_t* n_running, uint64_t* bytes_used,
+                         uint64_t* bytes_budget);
+
+/* Device bytes a query (g, J, K) holds while admitted (0 for bad arguments). */
+uint64_t im_query_footprint(const im_graph* g, int32_t J, int32_t K);
+
+void im_engine_free(im_engine* e);
+
+/* G independent queries in one engine, run to completion: seeds_out[i] is an
+ * int32[K[i]] host buffer, spread_out (optional) double[G]. */
+im_status im_select_seeds_batch(int32_t G, const im_graph* const* graphs, const int32_t* J, const uint64_t* seed,
+                                const int32_t* K, int32_t* const* seeds_out, double* spread_out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

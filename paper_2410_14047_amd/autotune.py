@@ -1,0 +1,68 @@
+"""Autotuner for the engine's scheduling parameters (lane-group sizes of the
+propagation kernel, sweeps/levels per step, dense-frontier threshold).
+
+Every candidate runs the same representative queries; the fastest candidate
+whose outputs are identical to the reference run is kept.  Scheduling never
+changes results (the register fixed point, the cascade and the exact argmax
+are schedule independent), so a candidate whose outputs differ is reported as
+an error rather than silently ranked.
+"""
+from __future__ import annotations
+
+import itertools
+import time
+from typing import Iterable, Optional
+
+from .binding import Engine, Graph
+
+DEFAULT = dict(group_first=64, group_rest=64, rounds_per_step=4, dense_div=16)
+
+
+def candidate_grid(J_max: int) -> list:
+    gs = [g for g in (16, 32, 64) if g >= (16 if J_max <= 1024 else 32 if J_max <= 2048 else 64)]
+    out = []
+    for gf, gr, r, d in itertools.product(gs, gs, (2, 4), (8, 16, 64)):
+        out.append(dict(group_first=gf, group_rest=gr, rounds_per_step=r, dense_div=d))
+    return out
+
+
+def _run(queries, tuning: dict, max_queries: int, stream=None):
+    E = Engine(max_queries=max_queries, stream=stream)
+    try:
+        E.set_tuning(**tuning)
+        t0 = time.perf_counter()
+        ids = [E.submit(G, J, s, K) for (G, J, s, K) in queries]
+        res = E.run()
+        dt = time.perf_counter() - t0
+        return dt, [res[i] for i in ids]
+    finally:
+        E.free()
+
+
+def _signature(results):
+    return [(tuple(r["seeds"].tolist()), tuple(r["T"].tolist()), r["est"].tobytes()) for r in results]
+
+
+def autotune(queries: Iterable, candidates: Optional[list] = None, max_queries: Optional[int] = None,
+             stream=None, repeats: int = 1) -> dict:
+    """queries: iterable of (Graph, J, seed, K).  Returns {"best": tuning,
+    "seconds": time of best, "table": [(tuning, seconds), ...]}."""
+    queries = list(queries)
+    if not queries:
+        raise ValueError("no queries to tune on")
+    mq = max_queries or len(queries)
+    J_max = max(q[1] for q in queries)
+    cands = candidates or candidate_grid(J_max)
+    _, ref = _run(queries, DEFAULT, mq, stream)  # warm-up and reference outputs
+    ref_sig = _signature(ref)
+    table = []
+    for tun in cands:
+        best_t = float("inf")
+        for _ in range(repeats):
+            dt, res = _run(queries, tun, mq, stream)
+            if _signature(res) != ref_sig:
+                raise RuntimeError(f"tuning {tun} changed the outputs")
+            best_t = min(best_t, dt)
+        table.append((tun, best_t))
+    table.sort(key=lambda x: x[1])
+    return {"best": table[0][0], "seconds": table[0][1], "table": table}

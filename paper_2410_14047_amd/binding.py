@@ -56,7 +56,11 @@ EXPORTS = [
     "im_last_error", "im_version", "im_set_profiling", "im_graph_load", "im_graph_info", "im_graph_free",
     "im_sketch_build", "im_select_seeds", "im_sketch_registers", "im_sketch_register_rows", "im_sketch_estimates",
     "im_sketch_stats", "im_sketch_sim_values", "im_sketch_free",
+    "im_engine_create", "im_engine_submit", "im_engine_step", "im_engine_poll", "im_engine_result",
+    "im_engine_info", "im_query_footprint", "im_engine_free", "im_select_seeds_batch",
+    "im_engine_set_tuning", "im_engine_get_tuning",
 ]
+_VOID = ("im_last_error", "im_graph_free", "im_sketch_free", "im_engine_free", "im_query_footprint")
 
 _lib = None
 
@@ -87,8 +91,21 @@ def lib() -> ctypes.CDLL:
         L.im_sketch_sim_values.argtypes = [P, P]
         L.im_sketch_free.argtypes = [P]
         L.im_sketch_free.restype = None
+        L.im_engine_create.argtypes = [i32, u64, P, P]
+        L.im_engine_submit.argtypes = [P, P, i32, u64, i32, P]
+        L.im_engine_step.argtypes = [P, P]
+        L.im_engine_poll.argtypes = [P, P, i32, P]
+        L.im_engine_result.argtypes = [P, i64, P, P, P, P, P]
+        L.im_engine_info.argtypes = [P, P, P, P, P]
+        L.im_query_footprint.argtypes = [P, i32, i32]
+        L.im_query_footprint.restype = u64
+        L.im_engine_free.argtypes = [P]
+        L.im_engine_free.restype = None
+        L.im_select_seeds_batch.argtypes = [i32, P, P, P, P, P, P, P]
+        L.im_engine_set_tuning.argtypes = [P, P]
+        L.im_engine_get_tuning.argtypes = [P, P]
         for name in EXPORTS:
-            if name not in ("im_last_error", "im_graph_free", "im_sketch_free"):
+            if name not in _VOID:
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -250,3 +267,107 @@ class Sketch:
             self.free()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- engines (batched / served queries)
+
+class im_tuning(ctypes.Structure):
+    _fields_ = [("group_first", ctypes.c_int32), ("group_rest", ctypes.c_int32),
+                ("rounds_per_step", ctypes.c_int32), ("dense_div", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def im_query_footprint(g, J: int, K: int) -> int:
+    return int(lib().im_query_footprint(g, J, K))
+
+
+class Engine:
+    """Many queries (graph, J, seed, K) advanced together by one native engine.
+    submit() raises IMError with status IM_ENOMEM when the query does not fit the
+    memory budget (nothing changes; retry after collecting results)."""
+
+    def __init__(self, max_queries: int = 64, hbm_budget_bytes: int = 0, stream=None):
+        out = ctypes.c_void_p()
+        _check(lib().im_engine_create(max_queries, hbm_budget_bytes, _stream(stream), ctypes.byref(out)))
+        self.handle = out
+        self._K = {}
+
+    def submit(self, graph: "Graph", J: int, seed: int, K: int) -> int:
+        qid = ctypes.c_int64()
+        _check(lib().im_engine_submit(self.handle, graph.handle, J, seed & (2**64 - 1), K, ctypes.byref(qid)))
+        self._K[qid.value] = K
+        return qid.value
+
+    def step(self) -> int:
+        n = ctypes.c_int32()
+        _check(lib().im_engine_step(self.handle, ctypes.byref(n)))
+        return n.value
+
+    def poll(self) -> list:
+        cap = max(1, len(self._K))
+        ids = np.zeros(cap, dtype=np.int64)
+        n = ctypes.c_int32()
+        _check(lib().im_engine_poll(self.handle, _p(ids), cap, ctypes.byref(n)))
+        return [int(x) for x in ids[: min(n.value, cap)]]
+
+    def result(self, qid: int) -> dict:
+        K = self._K[qid]
+        seeds = np.zeros(K, dtype=np.int32)
+        est = np.zeros(K, dtype=np.float64)
+        T = np.zeros(K, dtype=np.uint64)
+        spread = ctypes.c_double()
+        stats = im_stats()
+        _check(lib().im_engine_result(self.handle, qid, _p(seeds), ctypes.byref(spread), _p(est), _p(T),
+                                      ctypes.byref(stats)))
+        del self._K[qid]
+        return dict(seeds=seeds, spread=spread.value, est=est, T=T, stats=stats.as_dict())
+
+    def set_tuning(self, group_first: int = 64, group_rest: int = 64, rounds_per_step: int = 4,
+                   dense_div: int = 16) -> None:
+        t = im_tuning(group_first, group_rest, rounds_per_step, dense_div)
+        _check(lib().im_engine_set_tuning(self.handle, ctypes.byref(t)))
+
+    def get_tuning(self) -> dict:
+        t = im_tuning()
+        _check(lib().im_engine_get_tuning(self.handle, ctypes.byref(t)))
+        return t.as_dict()
+
+    def info(self) -> dict:
+        nq, nr = ctypes.c_int32(), ctypes.c_int32()
+        used, budget = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().im_engine_info(self.handle, ctypes.byref(nq), ctypes.byref(nr), ctypes.byref(used),
+                                    ctypes.byref(budget)))
+        return dict(queries=nq.value, running=nr.value, bytes_used=used.value, bytes_budget=budget.value)
+
+    def run(self) -> dict:
+        """Step until every admitted query finished; return {id: result}."""
+        while self.step() > 0:
+            pass
+        return {q: self.result(q) for q in self.poll()}
+
+    def free(self) -> None:
+        if self.handle:
+            lib().im_engine_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def im_select_seeds_batch(graphs, J, seeds, K, stream=None):
+    """G independent queries in one engine; returns (list of seed arrays, spreads)."""
+    G = len(graphs)
+    gh = (ctypes.c_void_p * G)(*[g.handle.value for g in graphs])
+    Ja = np.ascontiguousarray(J, dtype=np.int32)
+    Sa = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64))
+    Ka = np.ascontiguousarray(K, dtype=np.int32)
+    outs = [np.zeros(int(k), dtype=np.int32) for k in Ka]
+    optr = (ctypes.c_void_p * G)(*[o.ctypes.data for o in outs])
+    spread = np.zeros(G, dtype=np.float64)
+    _check(lib().im_select_seeds_batch(G, gh, _p(Ja), _p(Sa), _p(Ka), optr, _p(spread), _stream(stream)))
+    return outs, spread

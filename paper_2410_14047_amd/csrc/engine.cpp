@@ -1,0 +1,915 @@
+// Query engine: runs any number of influence-maximisation queries (graph, J,
+// seed, K) to completion together.  Every query follows Alg. 4 on one device
+// (build, then K x [estimate, argmax, cascade, score, rebuild test]); the
+// engine advances all active queries one stage per tick and issues one
+// batched launch per kernel kind per tick, so small queries share launches and
+// a single host synchronisation.  Each query's results are independent of the
+// others in the mix: the fixed point, the cascade and the exact argmax do not
+// depend on scheduling.
+//
+// Also implements the C ABI of sketches (one-query engines), engines and the
+// batch entry point.
+#include "handles.h"
+
+#include <chrono>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <memory>
+
+namespace imx {
+namespace {
+
+constexpr int kMaxRounds = 4;  // sweeps / cascade levels per tick at most (the counter rings hold 4)
+
+// Per-query counters the host reads back every tick (one array per engine).
+struct SlotStatus {
+    unsigned long long rows_changed[4];
+    unsigned long long T;
+    uint32_t qsize[4];
+    uint32_t act_count[4];
+    uint32_t chg_count[4];
+    uint32_t dense[4];
+    uint32_t ntouched;
+    uint32_t pad[5];
+};
+static_assert(sizeof(SlotStatus) == 128, "status record size");
+
+enum class Stage { Fill, Sweeps, Estimate, Pick, Levels, Finalize, Built, Done, Failed };
+
+double now_ms()
+{
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct Query {
+    int64_t id = 0;
+    int slot = -1;
+    const im_graph* g = nullptr;
+    int J = 0;
+    uint64_t seed = 0;
+    int K = 0;
+    bool park = false;  // stop after the initial build (sketch API)
+    Arena arena;
+    uint8_t* M = nullptr;
+    uint32_t* X = nullptr;
+    uint32_t* Ju = nullptr;
+    unsigned long long* Hu = nullptr;
+    uint8_t* is_seed = nullptr;
+    int32_t* best = nullptr;
+    SweepDev sw{};
+    CascadeDev c{};
+    ArgmaxScratch am{};
+    int32_t* seeds = nullptr;
+    uint32_t* pickJ = nullptr;
+    unsigned long long* pickH = nullptr;
+    PropCounters* pc = nullptr;
+    // host state
+    Stage stage = Stage::Fill;
+    bool fresh = true;      // the next fill is the sketch's first: every register uncovered
+    bool need_est = false;  // the next pick must recompute the estimate terms (after a build)
+    int sweep = 0;
+    int build_sweeps = 0;
+    int level = 1;
+    int k = 0;
+    uint32_t cascade_id = 0, level_base = 0;
+    uint64_t T_old = 0;
+    std::vector<uint64_t> T;
+    im_stats st{};
+    double t_build0 = 0, t_sel0 = 0;
+    int cap_K = 0;
+};
+
+class Engine {
+public:
+    Engine(hipStream_t st, int capacity, size_t budget) : st_(st), cap_(capacity), budget_(budget) {}
+    ~Engine()
+    {
+        for (Query* q : slots_)
+            if (q) release(q);
+        if (status_dev_) (void)hipFree(status_dev_);
+        if (args_dev_) (void)hipFree(args_dev_);
+        if (status_host_) (void)hipHostFree(status_host_);
+        if (args_host_) (void)hipHostFree(args_host_);
+        for (auto& e : ev_)
+            if (e) (void)hipEventDestroy(e);
+    }
+
+    im_status init()
+    {
+        if (cap_ < 1) return set_error(IM_EINVAL, "engine capacity must be >= 1");
+        slots_.assign(cap_, nullptr);
+        IMX_HIP(hipMalloc(&status_dev_, sizeof(SlotStatus) * cap_));
+        IMX_HIP(hipMemsetAsync(status_dev_, 0, sizeof(SlotStatus) * cap_, st_));
+        IMX_HIP(hipHostMalloc(reinterpret_cast<void**>(&status_host_), sizeof(SlotStatus) * cap_, 0));
+        args_cap_ = (size_t)cap_ * 8192 + (1u << 16);
+        IMX_HIP(hipMalloc(&args_dev_, args_cap_));
+        IMX_HIP(hipHostMalloc(reinterpret_cast<void**>(&args_host_), args_cap_, 0));
+        for (auto& e : ev_) IMX_HIP(hipEventCreate(&e));
+        const char* a = std::getenv("IMX_GROUP_FIRST");
+        const char* b = std::getenv("IMX_GROUP");
+        if (a) tune_.group_first = std::atoi(a);
+        if (b) tune_.group_rest = std::atoi(b);
+        IMX_HIP(hipStreamSynchronize(st_));
+        return IM_OK;
+    }
+
+    size_t used() const { return used_; }
+    size_t budget() const { return budget_; }
+    int active() const
+    {
+        int a = 0;
+        for (Query* q : slots_)
+            if (q && q->stage != Stage::Done && q->stage != Stage::Built && q->stage != Stage::Failed) ++a;
+        return a;
+    }
+
+    // Device bytes one query would hold.
+    static size_t footprint(const im_graph* g, int J, int K)
+    {
+        const size_t n = (size_t)g->n, nt = (size_t)std::max<int64_t>(g->ntasks, 1);
+        const size_t nit = (size_t)std::max<int64_t>(g->n_in_tasks, 1), bmw = (n + 31) / 32;
+        return n * (size_t)J + n * (4 + 8 + 1 + 4 * 3) + bmw * 12 + nt * 16 + nit * 4 + ((size_t)J + kTableWords) * 4 +
+               (size_t)kArgmaxBlocks * 16 + (size_t)std::max(K, 1) * 16 + 4096;
+    }
+
+    im_status submit(const im_graph* g, int J, uint64_t seed, int K, bool park, Query** out)
+    {
+        *out = nullptr;
+        if (!g) return set_error(IM_EINVAL, "graph is NULL");
+        if (J < 64 || J > kMaxJ || J % 64 != 0) return set_error(IM_EINVAL, "J must be a multiple of 64 in [64, 4096]");
+        if (!park && (K < 1 || K > g->n)) return set_error(IM_EINVAL, "K must be in [1, n]");
+        int slot = -1;
+        for (int i = 0; i < cap_; ++i)
+            if (!slots_[i]) {
+                slot = i;
+                break;
+            }
+        if (slot < 0) return set_error(IM_ENOMEM, "engine has no free query slot");
+        const size_t need = footprint(g, J, park ? 1 : K);
+        if (used_ + need > budget_) return set_error(IM_ENOMEM, "query does not fit in the engine's memory budget");
+        size_t free_b = 0, total_b = 0;
+        IMX_HIP(hipMemGetInfo(&free_b, &total_b));
+        if (need + (64u << 20) > free_b) return set_error(IM_ENOMEM, "query does not fit in device memory");
+
+        auto q = std::make_unique<Query>();
+        q->id = next_id_++;
+        q->slot = slot;
+        q->g = g;
+        q->J = J;
+        q->seed = seed;
+        q->K = K;
+        q->park = park;
+        const int64_t n = g->n;
+        const size_t nJ = (size_t)n * (size_t)J, bmw = (size_t)((n + 31) / 32);
+        const size_t nt = (size_t)std::max<int64_t>(g->ntasks, 1), nit = (size_t)std::max<int64_t>(g->n_in_tasks, 1);
+        Arena& A = q->arena;
+        if (A.alloc(&q->M, nJ) || A.alloc(&q->X, (size_t)J + kTableWords) || A.alloc(&q->Ju, n) || A.alloc(&q->Hu, n) ||
+            A.alloc(&q->sw.chg[0], bmw) || A.alloc(&q->sw.chg[1], bmw) || A.alloc(&q->sw.act_bm, bmw) ||
+            A.alloc(&q->sw.act_tasks[0], nt) || A.alloc(&q->sw.act_tasks[1], nt) || A.alloc(&q->sw.chg_list, nit) ||
+            A.alloc(&q->is_seed, n) || A.alloc(&q->best, 1) || A.alloc(&q->c.q[0], nt) || A.alloc(&q->c.q[1], nt) ||
+            A.alloc(&q->c.stamp, n) || A.alloc(&q->c.touched, n) || A.alloc(&q->c.touch_stamp, n) ||
+            A.alloc(&q->am.pJ, kArgmaxBlocks) || A.alloc(&q->am.pH, kArgmaxBlocks) || A.alloc(&q->am.pid, kArgmaxBlocks)) {
+            A.release();
+            return set_error(IM_ENOMEM, "device allocation failed");
+        }
+        if (!park && alloc_results(q.get(), K) != IM_OK) {
+            A.release();
+            return IM_ENOMEM;
+        }
+        if (profiling_level() >= 2 && A.alloc(&q->pc, 1)) {
+            A.release();
+            return set_error(IM_ENOMEM, "device allocation failed");
+        }
+        SlotStatus* S = status_dev_ + slot;
+        q->sw.rows_changed = S->rows_changed;
+        q->sw.act_count = S->act_count;
+        q->sw.chg_count = S->chg_count;
+        q->sw.dense = S->dense;
+        q->c.qsize = S->qsize;
+        q->c.T = &S->T;
+        q->c.ntouched = &S->ntouched;
+
+        hipError_t e = hipMemsetAsync(S, 0, sizeof(SlotStatus), st_);
+        if (e == hipSuccess) e = hipMemsetAsync(q->is_seed, 0, n, st_);
+        if (e == hipSuccess) e = hipMemsetAsync(q->c.stamp, 0, sizeof(uint32_t) * n, st_);
+        if (e == hipSuccess) e = hipMemsetAsync(q->c.touch_stamp, 0, sizeof(uint32_t) * n, st_);
+        if (e == hipSuccess && q->pc) e = hipMemsetAsync(q->pc, 0, sizeof(PropCounters), st_);
+        if (e == hipSuccess) e = launch_sim_values(seed, J, q->X, st_);
+        if (e != hipSuccess) {
+            A.release();
+            return set_error(IM_EDEVICE, std::string("query init: ") + hipGetErrorString(e));
+        }
+        q->stage = Stage::Fill;
+        q->fresh = true;
+        q->t_build0 = now_ms();
+        used_ += A.bytes;
+        slots_[slot] = q.get();
+        *out = q.release();
+        return IM_OK;
+    }
+
+    im_status alloc_results(Query* q, int K)
+    {
+        if (q->arena.alloc(&q->seeds, K) || q->arena.alloc(&q->pickJ, K) || q->arena.alloc(&q->pickH, K))
+            return set_error(IM_ENOMEM, "device allocation failed");
+        q->T.assign(K, 0);
+        q->cap_K = K;
+        return IM_OK;
+    }
+
+    // A parked (built) query starts selecting K seeds.
+    im_status resume(Query* q, int K)
+    {
+        if (q->stage != Stage::Built) return set_error(IM_ESTATE, "seeds were already selected on this sketch");
+        if (K < 1 || K > q->g->n) return set_error(IM_EINVAL, "K must be in [1, n]");
+        const size_t before = q->arena.bytes;
+        if (alloc_results(q, K) != IM_OK) return IM_ENOMEM;
+        used_ += q->arena.bytes - before;
+        q->K = K;
+        q->park = false;
+        q->stage = Stage::Pick;
+        q->t_sel0 = now_ms();
+        return IM_OK;
+    }
+
+    void release(Query* q)
+    {
+        if (q->slot >= 0 && q->slot < cap_ && slots_[q->slot] == q) slots_[q->slot] = nullptr;
+        used_ -= std::min(used_, q->arena.bytes);
+        q->arena.release();
+    }
+
+    void destroy(Query* q)
+    {
+        (void)hipStreamSynchronize(st_);
+        release(q);
+        delete q;
+    }
+
+    im_status step();
+
+    // Step until no query is in a running stage.
+    im_status run()
+    {
+        while (active() > 0)
+            if (im_status e = step()) return e;
+        return IM_OK;
+    }
+
+    im_status results(Query* q, int32_t* seeds, double* spread, double* est, uint64_t* T, im_stats* stats)
+    {
+        if (q->stage != Stage::Done) return set_error(IM_ESTATE, "query has not finished");
+        const int K = q->K;
+        std::vector<uint32_t> hJ(K);
+        std::vector<unsigned long long> hH(K);
+        std::vector<int32_t> hs(K);
+        IMX_HIP(hipMemcpyAsync(hs.data(), q->seeds, sizeof(int32_t) * K, hipMemcpyDeviceToHost, st_));
+        IMX_HIP(hipMemcpyAsync(hJ.data(), q->pickJ, sizeof(uint32_t) * K, hipMemcpyDeviceToHost, st_));
+        IMX_HIP(hipMemcpyAsync(hH.data(), q->pickH, sizeof(unsigned long long) * K, hipMemcpyDeviceToHost, st_));
+        IMX_HIP(hipStreamSynchronize(st_));
+        for (int k = 0; k < K; ++k)
+            if (hs[k] < 0) return set_error(IM_EDEVICE, "argmax found no candidate");
+        if (seeds) std::memcpy(seeds, hs.data(), sizeof(int32_t) * K);
+        if (est) {
+            const int J = q->J;
+            const double alpha = (J == 16) ? 0.673 : (J == 32) ? 0.697 : (J == 64) ? 0.709 : 0.7213 / (1.0 + 1.079 / (double)J);
+            const volatile double scale = alpha * 8589934592.0;
+            for (int k = 0; k < K; ++k) {
+                if (hJ[k] == 0) {
+                    est[k] = 0.0;
+                    continue;
+                }
+                const volatile double num = (double)((uint64_t)hJ[k] * hJ[k]);
+                const volatile double den = (double)J * (double)hH[k];
+                const volatile double qv = num / den;
+                est[k] = scale * qv;
+            }
+        }
+        if (T)
+            for (int k = 0; k < K; ++k) T[k] = q->T[k];
+        if (spread) *spread = (double)q->T[K - 1] / (double)q->J;
+        if (stats) *stats = q->st;
+        return IM_OK;
+    }
+
+    hipStream_t stream() const { return st_; }
+
+    im_status set_tuning(const im_tuning& t)
+    {
+        auto ok_gs = [](int v) { return v == 16 || v == 32 || v == 64; };
+        if (!ok_gs(t.group_first) || !ok_gs(t.group_rest) || t.rounds_per_step < 1 ||
+            t.rounds_per_step > kMaxRounds || t.dense_div < 1)
+            return set_error(IM_EINVAL, "tuning out of range");
+        tune_ = t;
+        return IM_OK;
+    }
+    const im_tuning& tuning() const { return tune_; }
+
+private:
+    // Argument records of one tick are packed into a pinned host buffer and
+    // copied to the device once, before the tick's launches.
+    template <class A>
+    const A* stage_args(const std::vector<A>& v)
+    {
+        const size_t off = (args_off_ + 255) & ~size_t(255);
+        const size_t nb = sizeof(A) * v.size();
+        if (off + nb > args_cap_) return nullptr;
+        std::memcpy(args_host_ + off, v.data(), nb);
+        args_off_ = off + nb;
+        return reinterpret_cast<const A*>(args_dev_ + off);
+    }
+
+    // Workgroup prefix for up to kMaxBatch queries, given per-query demands
+    // and a cap on the launch's total (scaled down proportionally, >= 1 each).
+    static Batch make_batch(const std::vector<int64_t>& want, int64_t cap)
+    {
+        Batch B{};
+        B.nq = (int)want.size();
+        int64_t tot = 0;
+        for (int64_t w : want) tot += std::max<int64_t>(w, 1);
+        B.wg0[0] = 0;
+        for (int i = 0; i < B.nq; ++i) {
+            int64_t w = std::max<int64_t>(want[i], 1);
+            if (cap > 0 && tot > cap) w = std::max<int64_t>(1, w * cap / tot);
+            B.wg0[i + 1] = B.wg0[i] + (int)w;
+        }
+        return B;
+    }
+
+    template <class A>
+    struct Launch {
+        std::vector<A> args;
+        std::vector<int64_t> want;
+        const A* dev = nullptr;
+        Batch B{};
+        int maxJ = 0;
+    };
+
+    hipStream_t st_;
+    int cap_;
+    size_t budget_;
+    size_t used_ = 0;
+    int64_t next_id_ = 1;
+    std::vector<Query*> slots_;
+    SlotStatus* status_dev_ = nullptr;
+    SlotStatus* status_host_ = nullptr;
+    uint8_t* args_dev_ = nullptr;
+    uint8_t* args_host_ = nullptr;
+    size_t args_cap_ = 0, args_off_ = 0;
+    hipEvent_t ev_[2 * kMaxRounds] = {};
+    im_tuning tune_{64, 64, 4, 16};
+};
+
+im_status Engine::step()
+{
+    std::vector<Query*> act;
+    for (Query* q : slots_)
+        if (q && (q->stage == Stage::Fill || q->stage == Stage::Sweeps || q->stage == Stage::Estimate ||
+                  q->stage == Stage::Pick || q->stage == Stage::Levels || q->stage == Stage::Finalize))
+            act.push_back(q);
+    if (act.empty()) return IM_OK;
+    const int cus = device_cu_count();
+    const int nr = tune_.rounds_per_step;
+    const int gs_first_ = tune_.group_first, gs_rest_ = tune_.group_rest;
+    args_off_ = 0;
+
+    // Chunks of at most kMaxBatch queries per launch.
+    auto chunks = [](const std::vector<Query*>& v) {
+        std::vector<std::vector<Query*>> out;
+        for (size_t i = 0; i < v.size(); i += kMaxBatch)
+            out.emplace_back(v.begin() + i, v.begin() + std::min(v.size(), i + kMaxBatch));
+        return out;
+    };
+    std::vector<Query*> fill_q, sweep_q, est_q, pick_q, level_q, fin_q;
+    for (Query* q : act) {
+        switch (q->stage) {
+        case Stage::Fill: fill_q.push_back(q); sweep_q.push_back(q); break;
+        case Stage::Sweeps: sweep_q.push_back(q); break;
+        case Stage::Estimate: est_q.push_back(q); break;
+        case Stage::Pick:
+            pick_q.push_back(q);
+            level_q.push_back(q);
+            break;
+        case Stage::Levels: level_q.push_back(q); break;
+        case Stage::Finalize: fin_q.push_back(q); break;
+        default: break;
+        }
+    }
+    for (Query* q : pick_q) {
+        ++q->cascade_id;
+        q->level = 1;
+    }
+
+    // ---- build all launches (argument records) of this tick
+    std::vector<Launch<FillArgs>> L_fill;
+    for (auto& ch : chunks(fill_q)) {
+        Launch<FillArgs> L;
+        for (Query* q : ch) {
+            L.args.push_back(FillArgs{q->M, q->g->n, q->J, q->fresh ? 1 : 0, q->seed});
+            L.want.push_back(std::min<int64_t>(16384, (q->g->n * (q->J / 4) + 2047) / 2048));
+        }
+        L_fill.push_back(std::move(L));
+    }
+    struct SweepRound {
+        std::vector<Launch<PrepArgs>> prep;
+        std::vector<Launch<PropArgs>> prop_first, prop_rest;
+        std::vector<Launch<MarkArgs>> mark;
+    };
+    std::vector<SweepRound> rounds(sweep_q.empty() ? 0 : nr);
+    int full_first = 0, full_rest = 0;
+    if (!sweep_q.empty()) {
+        int maxJ = 0;
+        for (Query* q : sweep_q) maxJ = std::max(maxJ, q->J);
+        IMX_HIP(propagate_full_grid(maxJ, gs_first_, profiling_level() >= 2, &full_first));
+        IMX_HIP(propagate_full_grid(maxJ, gs_rest_, profiling_level() >= 2, &full_rest));
+    }
+    for (int b = 0; b < (int)rounds.size(); ++b) {
+        for (auto& ch : chunks(sweep_q)) {
+            Launch<PrepArgs> P;
+            Launch<PropArgs> F, R;
+            Launch<MarkArgs> K;
+            for (Query* q : ch) {
+                const int s = q->sweep + b;
+                const GraphDev gd = q->g->dev();
+                const int64_t nwords = (q->g->n + 31) / 32;
+                P.args.push_back(PrepArgs{q->sw, nwords, s});
+                P.want.push_back(std::min<int64_t>(256, (nwords + 255) / 256));
+                PropArgs pa{gd,
+                            q->X,
+                            q->J,
+                            q->M,
+                            s == 0 ? nullptr : q->sw.act_tasks[s & 1],
+                            &q->sw.act_count[s & 3],
+                            q->sw.chg[s & 1],
+                            q->sw.chg[(s + 1) & 1],
+                            q->sw.chg_list,
+                            &q->sw.chg_count[s & 3],
+                            &q->sw.dense[s & 3],
+                            &q->sw.rows_changed[s & 3],
+                            q->pc};
+                Launch<PropArgs>& T = (s == 0) ? F : R;
+                const int lanes = propagate_group_size(q->J, s == 0 ? gs_first_ : gs_rest_);
+                T.args.push_back(pa);
+                T.want.push_back((q->g->ntasks * lanes + kWG - 1) / kWG);
+                T.maxJ = std::max(T.maxJ, q->J);
+                K.args.push_back(MarkArgs{gd, q->sw, s, tune_.dense_div});
+                K.want.push_back(std::min<int64_t>(cus * 4, (q->g->n_in_tasks + kWaves - 1) / kWaves));
+            }
+            rounds[b].prep.push_back(std::move(P));
+            if (!F.args.empty()) rounds[b].prop_first.push_back(std::move(F));
+            if (!R.args.empty()) rounds[b].prop_rest.push_back(std::move(R));
+            rounds[b].mark.push_back(std::move(K));
+        }
+    }
+    std::vector<Launch<EstArgs>> L_est;
+    std::vector<Query*> est_all = est_q;
+    for (Query* q : pick_q)
+        if (q->need_est) est_all.push_back(q);  // estimate terms after every build
+    for (auto& ch : chunks(est_all)) {
+        Launch<EstArgs> L;
+        for (Query* q : ch) {
+            L.args.push_back(EstArgs{q->M, q->g->n, q->J, q->Ju, q->Hu});
+            L.want.push_back(std::min<int64_t>(65536, (q->g->n + kWaves - 1) / kWaves));
+        }
+        L_est.push_back(std::move(L));
+    }
+    std::vector<Launch<ArgmaxArgs>> L_am;
+    std::vector<Launch<SeedArgs>> L_seed;
+    for (auto& ch : chunks(pick_q)) {
+        Launch<ArgmaxArgs> L;
+        Launch<SeedArgs> S;
+        for (Query* q : ch) {
+            const int nparts = (int)std::min<int64_t>(kArgmaxBlocks, (q->g->n + 255) / 256);
+            L.args.push_back(ArgmaxArgs{q->Ju, q->Hu, q->is_seed, q->g->n, q->am, q->best, std::max(nparts, 1)});
+            L.want.push_back(std::max(nparts, 1));
+            S.args.push_back(SeedArgs{q->g->dev(), q->best, q->k, q->M, q->J, q->is_seed, q->seeds, q->pickJ, q->pickH,
+                                      q->Ju, q->Hu, q->c, q->cascade_id, q->level_base + 1});
+            S.want.push_back(1);
+        }
+        L_am.push_back(std::move(L));
+        L_seed.push_back(std::move(S));
+    }
+    std::vector<std::vector<Launch<LevelArgs>>> L_lvl(level_q.empty() ? 0 : nr);
+    int full_level = 0;
+    if (!level_q.empty()) {
+        int maxJ = 0;
+        for (Query* q : level_q) maxJ = std::max(maxJ, q->J);
+        IMX_HIP(cascade_level_full_grid(maxJ, &full_level));
+    }
+    for (int b = 0; b < (int)L_lvl.size(); ++b)
+        for (auto& ch : chunks(level_q)) {
+            Launch<LevelArgs> L;
+            for (Query* q : ch) {
+                const int t = q->level + b;
+                L.args.push_back(LevelArgs{q->g->dev(), q->X, q->J, q->M, q->c, t, q->level_base + (uint32_t)t + 1,
+                                           q->cascade_id});
+                L.want.push_back((q->g->ntasks + kWaves - 1) / kWaves);
+                L.maxJ = std::max(L.maxJ, q->J);
+            }
+            L_lvl[b].push_back(std::move(L));
+        }
+    std::vector<Launch<FinArgs>> L_fin;
+    for (auto& ch : chunks(fin_q)) {
+        Launch<FinArgs> L;
+        for (Query* q : ch) {
+            L.args.push_back(FinArgs{q->M, q->J, q->Ju, q->Hu, q->c});
+            L.want.push_back(std::min<int64_t>(cus * 8, (q->g->n + 4 * kWaves - 1) / (4 * kWaves)));
+        }
+        L_fin.push_back(std::move(L));
+    }
+
+    // ---- stage argument records, one copy
+    auto finish = [&](auto& L, int64_t cap) -> bool {
+        L.dev = stage_args(L.args);
+        L.B = make_batch(L.want, cap);
+        return L.dev != nullptr;
+    };
+    bool ok = true;
+    for (auto& L : L_fill) ok &= finish(L, 0);
+    for (auto& R : rounds) {
+        for (auto& L : R.prep) ok &= finish(L, 0);
+        for (auto& L : R.prop_first) ok &= finish(L, full_first);
+        for (auto& L : R.prop_rest) ok &= finish(L, full_rest);
+        for (auto& L : R.mark) ok &= finish(L, (int64_t)cus * 4);
+    }
+    for (auto& L : L_est) ok &= finish(L, 0);
+    for (auto& L : L_am) ok &= finish(L, 0);
+    for (auto& L : L_seed) ok &= finish(L, 0);
+    for (auto& R : L_lvl)
+        for (auto& L : R) ok &= finish(L, full_level);
+    for (auto& L : L_fin) ok &= finish(L, 0);
+    if (!ok) return set_error(IM_EINVAL, "too many queries for one tick's argument buffer");
+    IMX_HIP(hipMemcpyAsync(args_dev_, args_host_, args_off_, hipMemcpyHostToDevice, st_));
+
+    // ---- launches, in dependency order
+    const bool stats = profiling_level() >= 2;
+    for (auto& L : L_fill) IMX_HIP(launch_fill(L.dev, L.B, st_));
+    int ne = 0;
+    for (auto& R : rounds) {
+        for (auto& L : R.prep) IMX_HIP(launch_sweep_prep(L.dev, L.B, st_));
+        IMX_HIP(hipEventRecord(ev_[2 * ne], st_));
+        for (auto& L : R.prop_first) IMX_HIP(launch_propagate(L.dev, L.B, L.maxJ, gs_first_, stats, st_));
+        for (auto& L : R.prop_rest) IMX_HIP(launch_propagate(L.dev, L.B, L.maxJ, gs_rest_, stats, st_));
+        IMX_HIP(hipEventRecord(ev_[2 * ne + 1], st_));
+        ++ne;
+        for (auto& L : R.mark) IMX_HIP(launch_mark(L.dev, L.B, st_));
+    }
+    for (auto& L : L_est) IMX_HIP(launch_estimate(L.dev, L.B, st_));
+    for (size_t i = 0; i < L_am.size(); ++i) {
+        Batch fin{};
+        fin.nq = L_am[i].B.nq;
+        for (int j = 0; j <= fin.nq; ++j) fin.wg0[j] = j;
+        IMX_HIP(launch_argmax(L_am[i].dev, L_am[i].B, fin, st_));
+        IMX_HIP(launch_cascade_seed(L_seed[i].dev, L_seed[i].B, st_));
+    }
+    for (auto& R : L_lvl)
+        for (auto& L : R) IMX_HIP(launch_cascade_level(L.dev, L.B, L.maxJ, st_));
+    for (auto& L : L_fin) IMX_HIP(launch_cascade_finalize(L.dev, L.B, st_));
+    IMX_HIP(hipMemcpyAsync(status_host_, status_dev_, sizeof(SlotStatus) * cap_, hipMemcpyDeviceToHost, st_));
+    IMX_HIP(hipStreamSynchronize(st_));
+
+    float prop_ms = 0.f;
+    for (int i = 0; i < ne; ++i) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ev_[2 * i], ev_[2 * i + 1]);
+        prop_ms += ms;
+    }
+
+    // ---- advance every query's state machine
+    for (Query* q : act) {
+        const SlotStatus& S = status_host_[q->slot];
+        switch (q->stage) {
+        case Stage::Fill:
+        case Stage::Sweeps: {
+            q->st.prop_kernel_ms += prop_ms / (double)sweep_q.size();
+            q->st.prop_launches += nr;
+            bool done = false;
+            for (int b = 0; b < nr && !done; ++b) {
+                ++q->build_sweeps;
+                if (S.rows_changed[(q->sweep + b) & 3] == 0) done = true;
+            }
+            q->sweep += nr;
+            if (done) {
+                q->st.total_sweeps += q->build_sweeps;
+                if (q->fresh) {
+                    q->st.build_sweeps = q->build_sweeps;
+                    q->st.build_ms = now_ms() - q->t_build0;
+                    q->t_sel0 = now_ms();
+                }
+                q->fresh = false;
+                q->build_sweeps = 0;
+                q->sweep = 0;
+                q->need_est = true;
+                q->stage = q->park ? Stage::Estimate : Stage::Pick;
+            } else if (q->build_sweeps > q->g->n + 2) {
+                q->stage = Stage::Failed;
+                return set_error(IM_EDEVICE, "propagation did not converge");
+            } else {
+                q->stage = Stage::Sweeps;
+            }
+            break;
+        }
+        case Stage::Estimate:
+            q->stage = Stage::Built;
+            q->need_est = false;
+            q->st.build_ms = now_ms() - q->t_build0;
+            break;
+        case Stage::Pick:
+        case Stage::Levels: {
+            q->need_est = false;
+            q->level += nr;
+            q->st.cascade_levels += nr;
+            if (S.qsize[q->level & 3] == 0) {
+                q->stage = Stage::Finalize;
+                q->level_base += (uint32_t)q->level + 2;
+            } else if (q->level > q->g->n + 8) {
+                q->stage = Stage::Failed;
+                return set_error(IM_EDEVICE, "cascade did not terminate");
+            } else {
+                q->stage = Stage::Levels;
+            }
+            break;
+        }
+        case Stage::Finalize: {
+            const uint64_t T = S.T;
+            q->T[q->k] = T;
+            ++q->k;
+            if (q->k >= q->K) {
+                q->stage = Stage::Done;
+                q->st.select_ms = now_ms() - q->t_sel0;
+            } else if (100 * (T - q->T_old) > T) {
+                q->T_old = T;
+                ++q->st.rebuilds;
+                q->stage = Stage::Fill;
+                q->sweep = 0;
+            } else {
+                q->stage = Stage::Pick;
+            }
+            break;
+        }
+        default: break;
+        }
+    }
+    return IM_OK;
+}
+
+}  // namespace imx
+
+using imx::Engine;
+using imx::Query;
+
+// ---------------------------------------------------------------------------
+// Sketches: one-query engines.
+
+struct im_sketch {
+    std::unique_ptr<Engine> eng;
+    Query* q = nullptr;
+    ~im_sketch()
+    {
+        if (q) eng->destroy(q);
+    }
+};
+
+struct im_engine {
+    std::unique_ptr<Engine> eng;
+    std::vector<Query*> queries;
+};
+
+namespace {
+
+im_status finish_prop_counters(Query* q)
+{
+    if (!q->pc) return IM_OK;
+    imx::PropCounters c{};
+    IMX_HIP(hipMemcpy(&c, q->pc, sizeof(c), hipMemcpyDeviceToHost));
+    im_stats& s = q->st;
+    s.prop_tasks = (int64_t)c.tasks;
+    s.prop_rows_read = (int64_t)c.rows_read;
+    s.prop_bytes_written = (int64_t)c.bytes_written;
+    s.prop_arcs_scanned = (int64_t)c.arcs_scanned;
+    s.prop_arcs_active = (int64_t)c.arcs_active;
+    s.prop_sectors = (int64_t)c.sectors;
+    s.prop_alg_bytes = 28.0 * c.tasks + 4.0 * c.arcs_scanned + 4.0 * c.arcs_active + 64.0 * c.sectors +
+                       (double)q->J * c.rows_read + (double)c.bytes_written +
+                       (double)((q->g->n + 31) / 32) * 4.0 * 2.0 * (double)s.prop_launches;
+    return IM_OK;
+}
+
+size_t device_free()
+{
+    size_t f = 0, t = 0;
+    (void)hipMemGetInfo(&f, &t);
+    return f;
+}
+
+}  // namespace
+
+extern "C" {
+
+im_status im_sketch_build(const im_graph* g, int32_t J, uint64_t seed, void* stream, im_sketch** out)
+{
+    if (!out) return imx::set_error(IM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!g) return imx::set_error(IM_EINVAL, "graph is NULL");
+    auto s = std::make_unique<im_sketch>();
+    s->eng = std::make_unique<Engine>(static_cast<hipStream_t>(stream), 1, device_free());
+    if (im_status e = s->eng->init()) return e;
+    if (im_status e = s->eng->submit(g, J, seed, 0, true, &s->q)) return e;
+    if (im_status e = s->eng->run()) return e;
+    *out = s.release();
+    return IM_OK;
+}
+
+im_status im_select_seeds(im_sketch* s, int32_t K, int32_t* seeds_host, double* spread_out, double* est_host,
+                          uint64_t* T_host, im_stats* stats_out)
+{
+    if (!s) return imx::set_error(IM_EINVAL, "sketch is NULL");
+    if (!seeds_host) return imx::set_error(IM_EINVAL, "seeds output is NULL");
+    if (im_status e = s->eng->resume(s->q, K)) return e;
+    if (im_status e = s->eng->run()) return e;
+    if (im_status e = finish_prop_counters(s->q)) return e;
+    return s->eng->results(s->q, seeds_host, spread_out, est_host, T_host, stats_out);
+}
+
+im_status im_sketch_registers(const im_sketch* s, uint8_t* regs_host)
+{
+    if (!s || !regs_host) return imx::set_error(IM_EINVAL, "NULL argument");
+    IMX_HIP(hipMemcpyAsync(regs_host, s->q->M, (size_t)s->q->g->n * (size_t)s->q->J, hipMemcpyDeviceToHost,
+                           s->eng->stream()));
+    IMX_HIP(hipStreamSynchronize(s->eng->stream()));
+    return IM_OK;
+}
+
+im_status im_sketch_register_rows(const im_sketch* s, const int32_t* rows_host, int32_t nrows, uint8_t* regs_host)
+{
+    if (!s || nrows < 0 || (nrows > 0 && (!rows_host || !regs_host))) return imx::set_error(IM_EINVAL, "NULL argument");
+    for (int32_t i = 0; i < nrows; ++i)
+        if (rows_host[i] < 0 || rows_host[i] >= s->q->g->n) return imx::set_error(IM_EINVAL, "row id out of range");
+    const size_t J = (size_t)s->q->J;
+    for (int32_t i = 0; i < nrows; ++i)
+        IMX_HIP(hipMemcpyAsync(regs_host + (size_t)i * J, s->q->M + (size_t)rows_host[i] * J, J, hipMemcpyDeviceToHost,
+                               s->eng->stream()));
+    IMX_HIP(hipStreamSynchronize(s->eng->stream()));
+    return IM_OK;
+}
+
+im_status im_sketch_estimates(const im_sketch* s, uint32_t* Ju_host, uint64_t* Hu_host)
+{
+    if (!s) return imx::set_error(IM_EINVAL, "sketch is NULL");
+    const int64_t n = s->q->g->n;
+    if (Ju_host)
+        IMX_HIP(hipMemcpyAsync(Ju_host, s->q->Ju, sizeof(uint32_t) * n, hipMemcpyDeviceToHost, s->eng->stream()));
+    if (Hu_host)
+        IMX_HIP(hipMemcpyAsync(Hu_host, s->q->Hu, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, s->eng->stream()));
+    IMX_HIP(hipStreamSynchronize(s->eng->stream()));
+    return IM_OK;
+}
+
+im_status im_sketch_stats(const im_sketch* s, im_stats* out)
+{
+    if (!s || !out) return imx::set_error(IM_EINVAL, "NULL argument");
+    *out = s->q->st;
+    return IM_OK;
+}
+
+im_status im_sketch_sim_values(const im_sketch* s, uint32_t* X_host)
+{
+    if (!s || !X_host) return imx::set_error(IM_EINVAL, "NULL argument");
+    IMX_HIP(hipMemcpyAsync(X_host, s->q->X, sizeof(uint32_t) * s->q->J, hipMemcpyDeviceToHost, s->eng->stream()));
+    IMX_HIP(hipStreamSynchronize(s->eng->stream()));
+    return IM_OK;
+}
+
+void im_sketch_free(im_sketch* s) { delete s; }
+
+// ---------------------------------------------------------------------------
+// Engines (batched and continuously admitted queries).
+
+im_status im_engine_create(int32_t max_queries, uint64_t hbm_budget_bytes, void* stream, im_engine** out)
+{
+    if (!out) return imx::set_error(IM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_queries < 1 || max_queries > 4096) return imx::set_error(IM_EINVAL, "max_queries must be in [1, 4096]");
+    auto e = std::make_unique<im_engine>();
+    const size_t budget = hbm_budget_bytes ? (size_t)hbm_budget_bytes : device_free();
+    e->eng = std::make_unique<Engine>(static_cast<hipStream_t>(stream), max_queries, budget);
+    if (im_status st = e->eng->init()) return st;
+    *out = e.release();
+    return IM_OK;
+}
+
+im_status im_engine_submit(im_engine* e, const im_graph* g, int32_t J, uint64_t seed, int32_t K, int64_t* query_id)
+{
+    if (!e || !query_id) return imx::set_error(IM_EINVAL, "NULL argument");
+    Query* q = nullptr;
+    if (im_status st = e->eng->submit(g, J, seed, K, false, &q)) return st;
+    e->queries.push_back(q);
+    *query_id = q->id;
+    return IM_OK;
+}
+
+im_status im_engine_step(im_engine* e, int32_t* n_running)
+{
+    if (!e) return imx::set_error(IM_EINVAL, "engine is NULL");
+    if (im_status st = e->eng->step()) return st;
+    if (n_running) *n_running = e->eng->active();
+    return IM_OK;
+}
+
+im_status im_engine_poll(im_engine* e, int64_t* done_ids, int32_t capacity, int32_t* n_done)
+{
+    if (!e || !n_done || (capacity > 0 && !done_ids)) return imx::set_error(IM_EINVAL, "NULL argument");
+    int32_t c = 0;
+    for (Query* q : e->queries)
+        if (q->stage == imx::Stage::Done) {
+            if (c < capacity) done_ids[c] = q->id;
+            ++c;
+        }
+    *n_done = c;
+    return IM_OK;
+}
+
+im_status im_engine_result(im_engine* e, int64_t query_id, int32_t* seeds_host, double* spread_out,
+                           double* est_host, uint64_t* T_host, im_stats* stats_out)
+{
+    if (!e || !seeds_host) return imx::set_error(IM_EINVAL, "NULL argument");
+    for (size_t i = 0; i < e->queries.size(); ++i) {
+        Query* q = e->queries[i];
+        if (q->id != query_id) continue;
+        if (im_status st = finish_prop_counters(q)) return st;
+        if (im_status st = e->eng->results(q, seeds_host, spread_out, est_host, T_host, stats_out)) return st;
+        e->eng->destroy(q);
+        e->queries.erase(e->queries.begin() + (ptrdiff_t)i);
+        return IM_OK;
+    }
+    return imx::set_error(IM_EINVAL, "unknown query id");
+}
+
+im_status im_engine_info(const im_engine* e, int32_t* n_queries, int32_t* n_running, uint64_t* bytes_used,
+                         uint64_t* bytes_budget)
+{
+    if (!e) return imx::set_error(IM_EINVAL, "engine is NULL");
+    if (n_queries) *n_queries = (int32_t)e->queries.size();
+    if (n_running) *n_running = e->eng->active();
+    if (bytes_used) *bytes_used = e->eng->used();
+    if (bytes_budget) *bytes_budget = e->eng->budget();
+    return IM_OK;
+}
+
+im_status im_engine_set_tuning(im_engine* e, const im_tuning* t)
+{
+    if (!e || !t) return imx::set_error(IM_EINVAL, "NULL argument");
+    return e->eng->set_tuning(*t);
+}
+
+im_status im_engine_get_tuning(const im_engine* e, im_tuning* t)
+{
+    if (!e || !t) return imx::set_error(IM_EINVAL, "NULL argument");
+    *t = e->eng->tuning();
+    return IM_OK;
+}
+
+uint64_t im_query_footprint(const im_graph* g, int32_t J, int32_t K)
+{
+    if (!g || J < 64 || J > imx::kMaxJ || K < 1) return 0;
+    return Engine::footprint(g, J, K);
+}
+
+void im_engine_free(im_engine* e)
+{
+    if (!e) return;
+    for (Query* q : e->queries) e->eng->destroy(q);
+    delete e;
+}
+
+im_status im_select_seeds_batch(int32_t G, const im_graph* const* graphs, const int32_t* J, const uint64_t* seed,
+                                const int32_t* K, int32_t* const* seeds_out, double* spread_out, void* stream)
+{
+    if (G < 1 || !graphs || !J || !seed || !K || !seeds_out) return imx::set_error(IM_EINVAL, "NULL argument");
+    im_engine* e = nullptr;
+    if (im_status st = im_engine_create(G, 0, stream, &e)) return st;
+    std::vector<int64_t> ids(G);
+    for (int32_t i = 0; i < G; ++i)
+        if (im_status st = im_engine_submit(e, graphs[i], J[i], seed[i], K[i], &ids[i])) {
+            im_engine_free(e);
+            return st;
+        }
+    if (im_status st = e->eng->run()) {
+        im_engine_free(e);
+        return st;
+    }
+    for (int32_t i = 0; i < G; ++i)
+        if (im_status st = im_engine_result(e, ids[i], seeds_out[i], spread_out ? &spread_out[i] : nullptr, nullptr,
+                                            nullptr, nullptr)) {
+            im_engine_free(e);
+            return st;
+        }
+    im_engine_free(e);
+    return IM_OK;
+}
+
+}  // extern "C"

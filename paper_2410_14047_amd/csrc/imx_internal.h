@@ -86,26 +86,125 @@ struct ArgmaxScratch {
     int32_t* pid;            // [kArgmaxBlocks]
 };
 
-hipError_t launch_thresholds(const float* p, uint32_t* W, int64_t m, hipStream_t st);
-// X holds J sorted values followed by the kBuckets+1 entry bucket table.
-hipError_t launch_sim_values(uint64_t seed, int J, uint32_t* X, hipStream_t st);
-hipError_t launch_fill(uint8_t* M, int64_t n, int J, uint64_t seed, bool first, hipStream_t st);
-hipError_t launch_sweep_prep(const SweepDev& s, int64_t n, int sweep, hipStream_t st);
+// ---------------------------------------------------------------------------
+// Batched launches.  One launch serves up to kMaxBatch queries: query i owns
+// workgroups wg0[i] .. wg0[i+1]-1 and the argument record args[i] (an array
+// in device memory).
+
+constexpr int kMaxBatch = 64;
+
+struct Batch {
+    int nq;
+    int wg0[kMaxBatch + 1];
+};
+
+struct FillArgs {
+    uint8_t* M;
+    int64_t n;
+    int J;
+    int first;  // fresh sketch: every register uncovered
+    uint64_t seed;
+};
+
+struct PrepArgs {
+    SweepDev s;
+    int64_t nwords;
+    int sweep;
+};
+
+struct PropArgs {
+    GraphDev g;
+    const uint32_t* X;            // sorted values + bucket table
+    int J;
+    uint8_t* M;
+    const int32_t* tasks;         // active tasks (nullptr: every task)
+    const uint32_t* task_count;   // device count of `tasks`
+    const uint32_t* chg_prev;
+    uint32_t* chg_next;
+    int32_t* chg_list;
+    uint32_t* chg_count;
+    const uint32_t* dense;        // nonzero: visit every task this sweep
+    unsigned long long* rows_changed;
+    PropCounters* stats;          // instrumented variant only
+};
+
+struct MarkArgs {
+    GraphDev g;
+    SweepDev s;
+    int sweep;
+    int dense_div;  // next sweep visits every task when more than n / dense_div rows changed
+};
+
+struct EstArgs {
+    const uint8_t* M;
+    int64_t n;
+    int J;
+    uint32_t* Ju;
+    unsigned long long* Hu;
+};
+
+struct ArgmaxArgs {
+    const uint32_t* Ju;
+    const unsigned long long* Hu;
+    const uint8_t* is_seed;
+    int64_t n;
+    ArgmaxScratch am;
+    int32_t* best;
+    int nparts;  // workgroups of the partial pass for this query
+};
+
+struct SeedArgs {
+    GraphDev g;
+    const int32_t* best;
+    int32_t k;
+    uint8_t* M;
+    int J;
+    uint8_t* is_seed;
+    int32_t* seeds;
+    uint32_t* pickJ;
+    unsigned long long* pickH;
+    const uint32_t* Ju;
+    const unsigned long long* Hu;
+    CascadeDev c;
+    uint32_t cascade_id;
+    uint32_t level_id1;
+};
+
+struct LevelArgs {
+    GraphDev g;
+    const uint32_t* X;
+    int J;
+    uint8_t* M;
+    CascadeDev c;
+    int t;
+    uint32_t level_id;    // stamp of Q_{t+1}
+    uint32_t cascade_id;
+};
+
+struct FinArgs {
+    uint8_t* M;
+    int J;
+    uint32_t* Ju;
+    unsigned long long* Hu;
+    CascadeDev c;
+};
+
+int device_cu_count();
 int propagate_group_size(int J, int requested);
-hipError_t launch_propagate(const GraphDev& g, const uint32_t* X, int J, uint8_t* M, const SweepDev& s, int sweep,
-                            int group_size, PropCounters* stats, hipStream_t st);
-hipError_t launch_mark(const GraphDev& g, const SweepDev& s, int sweep, hipStream_t st);
-hipError_t launch_estimate(const uint8_t* M, int64_t n, int J, uint32_t* Ju, unsigned long long* Hu,
-                           hipStream_t st);
-hipError_t launch_argmax(const uint32_t* Ju, const unsigned long long* Hu, const uint8_t* is_seed, int64_t n,
-                         const ArgmaxScratch& s, int32_t* best, hipStream_t st);
-hipError_t launch_cascade_seed(const GraphDev& g, const int32_t* best, int32_t k, uint8_t* M, int J,
-                               uint8_t* is_seed, int32_t* seeds, uint32_t* pickJ, unsigned long long* pickH,
-                               const uint32_t* Ju, const unsigned long long* Hu, const CascadeDev& c,
-                               uint32_t cascade_id, uint32_t level_id1, hipStream_t st);
-hipError_t launch_cascade_level(const GraphDev& g, const uint32_t* X, int J, uint8_t* M, const CascadeDev& c,
-                                int t, uint32_t level_id, uint32_t cascade_id, hipStream_t st);
-hipError_t launch_cascade_finalize(uint8_t* M, int J, uint32_t* Ju, unsigned long long* Hu, const CascadeDev& c,
-                                   hipStream_t st);
+hipError_t propagate_full_grid(int maxJ, int gs, bool stats, int* grid);
+hipError_t cascade_level_full_grid(int maxJ, int* grid);
+
+hipError_t launch_thresholds(const float* p, uint32_t* W, int64_t m, hipStream_t st);
+// X receives J sorted values followed by the kBuckets+1 entry bucket table.
+hipError_t launch_sim_values(uint64_t seed, int J, uint32_t* X, hipStream_t st);
+hipError_t launch_fill(const FillArgs* args, const Batch& B, hipStream_t st);
+hipError_t launch_sweep_prep(const PrepArgs* args, const Batch& B, hipStream_t st);
+hipError_t launch_propagate(const PropArgs* args, const Batch& B, int maxJ, int gs, bool stats, hipStream_t st);
+hipError_t launch_mark(const MarkArgs* args, const Batch& B, hipStream_t st);
+hipError_t launch_estimate(const EstArgs* args, const Batch& B, hipStream_t st);
+hipError_t launch_argmax(const ArgmaxArgs* args, const Batch& partial, const Batch& final_, hipStream_t st);
+hipError_t launch_cascade_seed(const SeedArgs* args, const Batch& B, hipStream_t st);
+hipError_t launch_cascade_level(const LevelArgs* args, const Batch& B, int maxJ, hipStream_t st);
+hipError_t launch_cascade_finalize(const FinArgs* args, const Batch& B, hipStream_t st);
 
 }  // namespace imx

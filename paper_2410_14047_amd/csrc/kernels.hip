@@ -261,6 +261,29 @@ __device__ __forceinline__ void wl_append_uniform(WaveList& w, int cnt, int32_t 
 }
 
 // ---------------------------------------------------------------------------
+// Batched launches: the workgroups of one launch are split among up to
+// kMaxBatch queries (query i owns workgroups wg0[i] .. wg0[i+1]-1 and reads
+// argument record args[i]); each workgroup works for exactly one query and
+// strides over that query's work with its local index and local grid size.
+
+__device__ __forceinline__ int batch_index(const Batch& B)
+{
+    int i = 0;
+#pragma unroll
+    for (int step = kMaxBatch / 2; step > 0; step >>= 1)
+        if (i + step < B.nq && B.wg0[i + step] <= (int)blockIdx.x) i += step;
+    return i;
+}
+
+#define IMX_BATCH_PROLOGUE(ArgsT)                                     \
+    const int bi_ = batch_index(B);                                   \
+    const ArgsT a = args[bi_];                                        \
+    const int64_t lb = (int64_t)blockIdx.x - B.wg0[bi_];              \
+    const int64_t lg = (int64_t)B.wg0[bi_ + 1] - B.wg0[bi_];          \
+    (void)lb;                                                         \
+    (void)lg
+
+// ---------------------------------------------------------------------------
 // a1: fixed-point thresholds W = min(2^31, floor(p * 2^31)).
 
 __global__ void k_thresholds(const float* __restrict__ p, uint32_t* __restrict__ W, int64_t m)
@@ -332,32 +355,30 @@ hipError_t launch_sim_values(uint64_t seed, int J, uint32_t* X, hipStream_t st)
 // a3: Fill-Sketches (Alg. 1).  One thread per 4 registers.  On a rebuild,
 // covered registers (0) stay 0.
 
-__global__ void k_fill(uint8_t* __restrict__ M, int64_t n, int J, uint64_t seed, int first)
+__global__ __launch_bounds__(256) void k_fill(const FillArgs* __restrict__ args, Batch B)
 {
-    const int64_t words_per_row = J / 4;
-    const int64_t total = n * words_per_row;
-    uint32_t* M32 = reinterpret_cast<uint32_t*>(M);
-    for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < total; d += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t u = (uint32_t)(d / words_per_row);
-        uint32_t j0 = (uint32_t)(d - (int64_t)u * words_per_row) * 4u;
-        uint32_t pre = rank_prefix(seed, u);
-        uint32_t old = first ? 0xffffffffu : M32[d];
+    IMX_BATCH_PROLOGUE(FillArgs);
+    const int64_t words_per_row = a.J / 4;
+    const int64_t total = a.n * words_per_row;
+    uint32_t* M32 = reinterpret_cast<uint32_t*>(a.M);
+    for (int64_t d = lb * blockDim.x + threadIdx.x; d < total; d += lg * blockDim.x) {
+        const uint32_t u = (uint32_t)(d / words_per_row);
+        const uint32_t j0 = (uint32_t)(d - (int64_t)u * words_per_row) * 4u;
+        const uint32_t pre = rank_prefix(a.seed, u);
+        const uint32_t old = a.first ? 0xffffffffu : M32[d];
         uint32_t out = 0;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            uint32_t r = ((old >> (8 * b)) & 0xffu) ? rank_of(pre, j0 + b) : 0u;
+            const uint32_t r = ((old >> (8 * b)) & 0xffu) ? rank_of(pre, j0 + b) : 0u;
             out |= r << (8 * b);
         }
         M32[d] = out;
     }
 }
 
-hipError_t launch_fill(uint8_t* M, int64_t n, int J, uint64_t seed, bool first, hipStream_t st)
+hipError_t launch_fill(const FillArgs* args, const Batch& B, hipStream_t st)
 {
-    int64_t total = n * (J / 4);
-    int64_t blocks = (total + 255) / 256;
-    if (blocks > 262144) blocks = 262144;
-    hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, st, M, n, J, seed, first ? 1 : 0);
+    hipLaunchKernelGGL(k_fill, dim3(B.wg0[B.nq]), dim3(256), 0, st, args, B);
     return hipGetLastError();
 }
 
@@ -384,21 +405,7 @@ hipError_t launch_fill(uint8_t* M, int64_t n, int J, uint64_t seed, bool first, 
 //     are queued; k_mark turns them into the next sweep's active task list,
 //     unless so many rows changed that the next sweep visits every task.
 
-struct PropArgs {
-    GraphDev g;
-    const uint32_t* X;
-    int J;
-    uint8_t* M;
-    const int32_t* tasks;         // active tasks (nullptr: every task)
-    const uint32_t* task_count;   // device count of `tasks`
-    const uint32_t* chg_prev;
-    uint32_t* chg_next;
-    int32_t* chg_list;
-    uint32_t* chg_count;
-    const uint32_t* dense;        // nonzero: visit every task this sweep
-    unsigned long long* rows_changed;
-    PropCounters* stats;          // instrumented variant only
-};
+
 
 constexpr int kPropBufCap = 256;  // staging entries per wave for the changed in-task list
 
@@ -469,8 +476,9 @@ __device__ __forceinline__ void lds_merge_word(uint32_t* w, uint32_t* dirty, int
 }
 
 template <int GS, int DPLG, bool STATS>
-__global__ __launch_bounds__(kWG) void k_propagate(PropArgs a)
+__global__ __launch_bounds__(kWG) void k_propagate(const PropArgs* __restrict__ args, Batch B)
 {
+    IMX_BATCH_PROLOGUE(PropArgs);
     constexpr int NG = 64 / GS;
     constexpr int GB = group_buf_words<GS, STATS>();
     extern __shared__ uint32_t smem[];
@@ -508,9 +516,9 @@ __global__ __launch_bounds__(kWG) void k_propagate(PropArgs a)
     const bool all = a.tasks == nullptr || *a.dense != 0u;
     const int32_t* tasks = all ? nullptr : a.tasks;
     const int64_t count = all ? g.ntasks : (int64_t)*a.task_count;
-    const int64_t ngroups = (int64_t)gridDim.x * kWaves * NG;
+    const int64_t ngroups = lg * kWaves * NG;
 
-    for (int64_t qb = ((int64_t)blockIdx.x * kWaves + wave) * NG; qb < count; qb += ngroups) {
+    for (int64_t qb = (lb * kWaves + wave) * NG; qb < count; qb += ngroups) {
         const int64_t q = qb + gi;
         const bool valid = q < count;
         int32_t u = 0;
@@ -726,38 +734,45 @@ static int cu_count()
 }
 
 template <int GS, int DPLG, bool STATS>
-static hipError_t launch_propagate_t(const PropArgs& a, hipStream_t st)
+static size_t propagate_lds(int J)
 {
     constexpr int NG = 64 / GS;
-    const size_t lds = sizeof(uint32_t) * ((size_t)a.J + kTableWords + (size_t)kWaves * kPropBufCap +
-                                           (size_t)kWaves * NG * ((size_t)(a.J / 4) + group_buf_words<GS, STATS>()));
-    static size_t lds_set = 0;
-    static int per_cu = 0;
-    if (lds_set != lds) {
-        hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_propagate<GS, DPLG, STATS>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (err != hipSuccess) return err;
-        err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_propagate<GS, DPLG, STATS>, kWG, lds);
-        if (err != hipSuccess) return err;
-        if (per_cu < 1) per_cu = 1;
-        lds_set = lds;
-    }
-    int grid = cu_count() * per_cu;
-    const int64_t need = (a.g.ntasks + kWaves * NG - 1) / (kWaves * NG);
-    if (need < grid) grid = (int)(need > 0 ? need : 1);
-    hipLaunchKernelGGL((k_propagate<GS, DPLG, STATS>), dim3(grid), dim3(kWG), lds, st, a);
-    return hipGetLastError();
+    return sizeof(uint32_t) * ((size_t)J + kTableWords + (size_t)kWaves * kPropBufCap +
+                               (size_t)kWaves * NG * ((size_t)(J / 4) + group_buf_words<GS, STATS>()));
 }
 
-template <int GS, bool STATS>
-static hipError_t launch_propagate_g(const PropArgs& a, hipStream_t st)
+// Occupancy-derived workgroups per CU of one propagation configuration.
+template <int GS, int DPLG, bool STATS>
+static hipError_t propagate_setup(int J, int* per_cu)
 {
-    const int dpl = (a.J / 4 + GS - 1) / GS;  // 32-bit words per lane
-    if (dpl <= 1) return launch_propagate_t<GS, 1, STATS>(a, st);
-    if (dpl <= 2) return launch_propagate_t<GS, 2, STATS>(a, st);
-    if (dpl <= 4) return launch_propagate_t<GS, 4, STATS>(a, st);
-    if (dpl <= 8) return launch_propagate_t<GS, 8, STATS>(a, st);
-    return launch_propagate_t<GS, 16, STATS>(a, st);
+    const size_t lds = propagate_lds<GS, DPLG, STATS>(J);
+    static size_t lds_set = 0, attr_set = 0;
+    static int cached = 0;
+    if (lds_set != lds) {
+        if (lds > attr_set) {
+            hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_propagate<GS, DPLG, STATS>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (err != hipSuccess) return err;
+            attr_set = lds;
+        }
+        hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&cached, k_propagate<GS, DPLG, STATS>, kWG, lds);
+        if (err != hipSuccess) return err;
+        if (cached < 1) cached = 1;
+        lds_set = lds;
+    }
+    *per_cu = cached;
+    return hipSuccess;
+}
+
+template <int GS, int DPLG, bool STATS>
+static hipError_t launch_propagate_t(const PropArgs* args, const Batch& B, int maxJ, hipStream_t st)
+{
+    int per_cu = 0;
+    hipError_t err = propagate_setup<GS, DPLG, STATS>(maxJ, &per_cu);
+    if (err != hipSuccess) return err;
+    const size_t lds = propagate_lds<GS, DPLG, STATS>(maxJ);
+    hipLaunchKernelGGL((k_propagate<GS, DPLG, STATS>), dim3(B.wg0[B.nq]), dim3(kWG), lds, st, args, B);
+    return hipGetLastError();
 }
 
 // Lane-group size for a row width: the smallest of 16/32/64 lanes that keeps
@@ -769,44 +784,55 @@ int propagate_group_size(int J, int requested)
     return gs;
 }
 
-template <bool STATS>
-static hipError_t launch_propagate_s(const PropArgs& a, int gs, hipStream_t st)
+// Calls f.template operator()<GS, DPLG, STATS>() for the configuration of
+// (maxJ, gs, stats).
+template <class F>
+static hipError_t propagate_dispatch(int maxJ, int gs, bool stats, F&& f)
 {
-    if (gs == 16) return launch_propagate_g<16, STATS>(a, st);
-    if (gs == 32) return launch_propagate_g<32, STATS>(a, st);
-    return launch_propagate_g<64, STATS>(a, st);
+    const int g = propagate_group_size(maxJ, gs);
+    const int dpl = (maxJ / 4 + g - 1) / g;
+#define IMX_PD(G, D)                                                                         \
+    if (g == G && dpl <= D) return stats ? f.template operator()<G, D, true>() : f.template operator()<G, D, false>();
+    IMX_PD(16, 1) IMX_PD(16, 2) IMX_PD(16, 4) IMX_PD(16, 8) IMX_PD(16, 16)
+    IMX_PD(32, 1) IMX_PD(32, 2) IMX_PD(32, 4) IMX_PD(32, 8) IMX_PD(32, 16)
+    IMX_PD(64, 1) IMX_PD(64, 2) IMX_PD(64, 4) IMX_PD(64, 8) IMX_PD(64, 16)
+#undef IMX_PD
+    return hipErrorInvalidValue;
 }
 
-hipError_t launch_propagate(const GraphDev& g, const uint32_t* X, int J, uint8_t* M, const SweepDev& s, int sweep,
-                            int group_size, PropCounters* stats, hipStream_t st)
+hipError_t propagate_full_grid(int maxJ, int gs, bool stats, int* grid)
 {
-    if (g.ntasks == 0) return hipSuccess;
-    PropArgs a{g,
-               X,
-               J,
-               M,
-               sweep == 0 ? nullptr : s.act_tasks[sweep & 1],
-               &s.act_count[sweep & 3],
-               s.chg[sweep & 1],
-               s.chg[(sweep + 1) & 1],
-               s.chg_list,
-               &s.chg_count[sweep & 3],
-               &s.dense[sweep & 3],
-               &s.rows_changed[sweep & 3],
-               stats};
-    const int gs = propagate_group_size(J, group_size);
-    return stats ? launch_propagate_s<true>(a, gs, st) : launch_propagate_s<false>(a, gs, st);
+    return propagate_dispatch(maxJ, gs, stats, [&]<int G, int D, bool S>() -> hipError_t {
+        int per_cu = 0;
+        hipError_t e = propagate_setup<G, D, S>(maxJ, &per_cu);
+        *grid = cu_count() * per_cu;
+        return e;
+    });
+}
+
+int propagate_lanes_per_task(int maxJ, int gs) { return propagate_group_size(maxJ, gs); }
+
+hipError_t launch_propagate(const PropArgs* args, const Batch& B, int maxJ, int gs, bool stats, hipStream_t st)
+{
+    return propagate_dispatch(maxJ, gs, stats, [&]<int G, int D, bool S>() -> hipError_t {
+        return launch_propagate_t<G, D, S>(args, B, maxJ, st);
+    });
 }
 
 // Before sweep s: clear the bitmap sweep s writes, the activation bitmap and
-// the counters sweep s and its mark step accumulate into.
-__global__ void k_sweep_prep(SweepDev s, int64_t nwords, int sweep)
+// the counters sweep s and its mark step accumulate into.  Sweep 0 (right
+// after a fill) also marks every row as changed.
+__global__ __launch_bounds__(256) void k_sweep_prep(const PrepArgs* __restrict__ args, Batch B)
 {
-    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    IMX_BATCH_PROLOGUE(PrepArgs);
+    const SweepDev& s = a.s;
+    const int sweep = a.sweep;
+    const int64_t i0 = lb * blockDim.x + threadIdx.x;
     uint32_t* nxt = s.chg[(sweep + 1) & 1];
-    for (int64_t i = i0; i < nwords; i += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t i = i0; i < a.nwords; i += lg * blockDim.x) {
         nxt[i] = 0u;
         s.act_bm[i] = 0u;
+        if (sweep == 0) s.chg[0][i] = 0xffffffffu;
     }
     if (i0 == 0) {
         s.rows_changed[sweep & 3] = 0ull;
@@ -815,34 +841,32 @@ __global__ void k_sweep_prep(SweepDev s, int64_t nwords, int sweep)
     }
 }
 
-hipError_t launch_sweep_prep(const SweepDev& s, int64_t n, int sweep, hipStream_t st)
+hipError_t launch_sweep_prep(const PrepArgs* args, const Batch& B, hipStream_t st)
 {
-    const int64_t nwords = (n + 31) / 32;
-    int64_t blocks = (nwords + 255) / 256;
-    if (blocks > 2048) blocks = 2048;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_sweep_prep, dim3((unsigned)blocks), dim3(256), 0, st, s, nwords, sweep);
+    hipLaunchKernelGGL(k_sweep_prep, dim3(B.wg0[B.nq]), dim3(256), 0, st, args, B);
     return hipGetLastError();
 }
-
-constexpr int kDenseFraction = 16;  // dense next sweep when more than n/16 rows changed
 
 // Mark step of sweep s: every source w of an in-arc of a changed row becomes
 // active for sweep s+1 (once, through the activation bitmap) and its
 // out-tasks are appended to the next active task list.
-__global__ __launch_bounds__(kWG) void k_mark(GraphDev g, SweepDev s, int sweep)
+__global__ __launch_bounds__(kWG) void k_mark(const MarkArgs* __restrict__ args, Batch B)
 {
+    IMX_BATCH_PROLOGUE(MarkArgs);
+    const GraphDev& g = a.g;
+    const SweepDev& s = a.s;
+    const int sweep = a.sweep;
     __shared__ int32_t wbuf[kWaves][kWaveBufCap];
     const int lane = lane_id();
-    // Many changed rows: the next sweep visits every task (with per-arc
-    // changed-head tests) instead of building a list.
-    const bool dense = s.rows_changed[sweep & 3] * (unsigned long long)kDenseFraction > (unsigned long long)g.n;
-    if (blockIdx.x == 0 && threadIdx.x == 0) s.dense[(sweep + 1) & 3] = dense ? 1u : 0u;
+    // Many changed rows (more than n / dense_div): the next sweep visits every
+    // task (with per-arc changed-head tests) instead of building a list.
+    const bool dense = s.rows_changed[sweep & 3] * (unsigned long long)a.dense_div > (unsigned long long)g.n;
+    if (lb == 0 && threadIdx.x == 0) s.dense[(sweep + 1) & 3] = dense ? 1u : 0u;
     if (dense) return;
     const uint32_t count = s.chg_count[sweep & 3];
     WaveList nxt{wbuf[threadIdx.x >> 6], 0, s.act_tasks[(sweep + 1) & 1], &s.act_count[(sweep + 1) & 3]};
-    const int64_t nw = (int64_t)gridDim.x * kWaves;
-    for (int64_t q = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); q < (int64_t)count; q += nw) {
+    const int64_t nw = lg * kWaves;
+    for (int64_t q = lb * kWaves + (threadIdx.x >> 6); q < (int64_t)count; q += nw) {
         const int32_t it = s.chg_list[q];
         const int32_t v = g.in_task_v[it];
         const int64_t e0 = g.in_task_e0[it];
@@ -866,9 +890,9 @@ __global__ __launch_bounds__(kWG) void k_mark(GraphDev g, SweepDev s, int sweep)
     wl_flush(nxt);
 }
 
-hipError_t launch_mark(const GraphDev& g, const SweepDev& s, int sweep, hipStream_t st)
+hipError_t launch_mark(const MarkArgs* args, const Batch& B, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_mark, dim3(cu_count() * 4), dim3(kWG), 0, st, g, s, sweep);
+    hipLaunchKernelGGL(k_mark, dim3(B.wg0[B.nq]), dim3(kWG), 0, st, args, B);
     return hipGetLastError();
 }
 
@@ -876,21 +900,21 @@ hipError_t launch_mark(const GraphDev& g, const SweepDev& s, int sweep, hipStrea
 // a5: estimate terms per vertex (Eq. 7 harmonic form over uncovered registers):
 // Ju = #registers != 0, Hu = sum of 2^(33 - M).  One wave per row.
 
-__global__ __launch_bounds__(kWG) void k_estimate(const uint8_t* __restrict__ M, int64_t n, int J,
-                                                   uint32_t* __restrict__ Ju, unsigned long long* __restrict__ Hu)
+__global__ __launch_bounds__(kWG) void k_estimate(const EstArgs* __restrict__ args, Batch B)
 {
+    IMX_BATCH_PROLOGUE(EstArgs);
     const int lane = lane_id();
-    const int Jw = J >> 2;
-    const int64_t nw = (int64_t)gridDim.x * kWaves;
-    for (int64_t v = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); v < n; v += nw) {
-        const uint32_t* row = reinterpret_cast<const uint32_t*>(M + (size_t)v * (size_t)J);
+    const int Jw = a.J >> 2;
+    const int64_t nw = lg * kWaves;
+    for (int64_t v = lb * kWaves + (threadIdx.x >> 6); v < a.n; v += nw) {
+        const uint32_t* row = reinterpret_cast<const uint32_t*>(a.M + (size_t)v * (size_t)a.J);
         uint32_t c = 0;
         unsigned long long h = 0;
         for (int idx = lane; idx < Jw; idx += 64) {
-            uint32_t d = row[idx];
+            const uint32_t d = row[idx];
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                uint32_t r = (d >> (8 * b)) & 0xffu;
+                const uint32_t r = (d >> (8 * b)) & 0xffu;
                 if (r) {
                     ++c;
                     h += 1ull << (33u - r);
@@ -900,17 +924,15 @@ __global__ __launch_bounds__(kWG) void k_estimate(const uint8_t* __restrict__ M,
         c = wave_sum_u32(c);
         h = wave_sum_u64(h);
         if (lane == 0) {
-            Ju[v] = c;
-            Hu[v] = h;
+            a.Ju[v] = c;
+            a.Hu[v] = h;
         }
     }
 }
 
-hipError_t launch_estimate(const uint8_t* M, int64_t n, int J, uint32_t* Ju, unsigned long long* Hu, hipStream_t st)
+hipError_t launch_estimate(const EstArgs* args, const Batch& B, hipStream_t st)
 {
-    int64_t blocks = (n + kWaves - 1) / kWaves;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_estimate, dim3((unsigned)blocks), dim3(kWG), 0, st, M, n, J, Ju, Hu);
+    hipLaunchKernelGGL(k_estimate, dim3(B.wg0[B.nq]), dim3(kWG), 0, st, args, B);
     return hipGetLastError();
 }
 
@@ -966,44 +988,40 @@ __device__ void block_reduce_best(Cand& c)
     c = Cand{sJ[0], sH[0], sI[0]};
 }
 
-__global__ __launch_bounds__(256) void k_argmax_partial(const uint32_t* __restrict__ Ju,
-                                                         const unsigned long long* __restrict__ Hu,
-                                                         const uint8_t* __restrict__ is_seed, int64_t n,
-                                                         ArgmaxScratch s)
+__global__ __launch_bounds__(256) void k_argmax_partial(const ArgmaxArgs* __restrict__ args, Batch B)
 {
+    IMX_BATCH_PROLOGUE(ArgmaxArgs);
     Cand best{0u, 0ull, -1};
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-        if (is_seed[v]) continue;
-        Cand c{Ju[v], Hu[v], (int32_t)v};
+    for (int64_t v = lb * blockDim.x + threadIdx.x; v < a.n; v += lg * blockDim.x) {
+        if (a.is_seed[v]) continue;
+        Cand c{a.Ju[v], a.Hu[v], (int32_t)v};
         if (better(c, best)) best = c;
     }
     block_reduce_best(best);
     if (threadIdx.x == 0) {
-        s.pJ[blockIdx.x] = best.J;
-        s.pH[blockIdx.x] = best.H;
-        s.pid[blockIdx.x] = best.id;
+        a.am.pJ[lb] = best.J;
+        a.am.pH[lb] = best.H;
+        a.am.pid[lb] = best.id;
     }
 }
 
-__global__ __launch_bounds__(256) void k_argmax_final(ArgmaxScratch s, int nparts, int32_t* best_out)
+// One workgroup per query reduces that query's a.nparts partial winners.
+__global__ __launch_bounds__(256) void k_argmax_final(const ArgmaxArgs* __restrict__ args, Batch B)
 {
+    IMX_BATCH_PROLOGUE(ArgmaxArgs);
     Cand best{0u, 0ull, -1};
-    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
-        Cand c{s.pJ[i], s.pH[i], s.pid[i]};
+    for (int i = threadIdx.x; i < a.nparts; i += blockDim.x) {
+        Cand c{a.am.pJ[i], a.am.pH[i], a.am.pid[i]};
         if (better(c, best)) best = c;
     }
     block_reduce_best(best);
-    if (threadIdx.x == 0) *best_out = best.id;
+    if (threadIdx.x == 0) *a.best = best.id;
 }
 
-hipError_t launch_argmax(const uint32_t* Ju, const unsigned long long* Hu, const uint8_t* is_seed, int64_t n,
-                         const ArgmaxScratch& s, int32_t* best, hipStream_t st)
+hipError_t launch_argmax(const ArgmaxArgs* args, const Batch& partial, const Batch& final_, hipStream_t st)
 {
-    int64_t blocks = (n + 255) / 256;
-    if (blocks > kArgmaxBlocks) blocks = kArgmaxBlocks;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_argmax_partial, dim3((unsigned)blocks), dim3(256), 0, st, Ju, Hu, is_seed, n, s);
-    hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(256), 0, st, s, (int)blocks, best);
+    hipLaunchKernelGGL(k_argmax_partial, dim3(partial.wg0[partial.nq]), dim3(256), 0, st, args, partial);
+    hipLaunchKernelGGL(k_argmax_final, dim3(final_.wg0[final_.nq]), dim3(256), 0, st, args, final_);
     return hipGetLastError();
 }
 
@@ -1016,26 +1034,25 @@ __device__ __forceinline__ bool uncovered(uint32_t b) { return b >= 1u && b <= 3
 
 // Level 0: the pick s becomes a seed and is covered in every simulation where
 // it is not yet covered; its out-tasks form frontier Q_1.
-__global__ __launch_bounds__(64) void k_cascade_seed(GraphDev g, const int32_t* __restrict__ best, int32_t k,
-                                                      uint8_t* M, int J, uint8_t* is_seed, int32_t* seeds,
-                                                      uint32_t* pickJ, unsigned long long* pickH, const uint32_t* Ju,
-                                                      const unsigned long long* Hu, CascadeDev c,
-                                                      uint32_t cascade_id, uint32_t level_id1)
+__global__ __launch_bounds__(64) void k_cascade_seed(const SeedArgs* __restrict__ args, Batch B)
 {
+    IMX_BATCH_PROLOGUE(SeedArgs);
+    const GraphDev& g = a.g;
+    const CascadeDev& c = a.c;
     const int lane = lane_id();
-    const int32_t s = *best;
+    const int32_t s = *a.best;
     if (s < 0) {  // no candidate (cannot happen for K <= n); leave an empty cascade
         if (lane == 0) {
-            seeds[k] = -1;
+            a.seeds[a.k] = -1;
             c.qsize[0] = c.qsize[1] = c.qsize[2] = c.qsize[3] = 0;
             *c.ntouched = 0;
         }
         return;
     }
-    uint32_t* row = reinterpret_cast<uint32_t*>(M + (size_t)s * (size_t)J);
+    uint32_t* row = reinterpret_cast<uint32_t*>(a.M + (size_t)s * (size_t)a.J);
     bool any = false;
     const uint32_t mk = marker(0);
-    for (int idx = lane; idx < (J >> 2); idx += 64) {
+    for (int idx = lane; idx < (a.J >> 2); idx += 64) {
         const uint32_t d = row[idx];
         const uint32_t um = uncovered_mask4(d);
         if (um) {
@@ -1047,28 +1064,24 @@ __global__ __launch_bounds__(64) void k_cascade_seed(GraphDev g, const int32_t* 
     const int32_t t0 = g.task_start[s], nt = anyw ? g.task_start[s + 1] - t0 : 0;
     for (int q = lane; q < nt; q += 64) c.q[1][q] = t0 + q;
     if (lane == 0) {
-        is_seed[s] = 1;
-        seeds[k] = s;
-        pickJ[k] = Ju[s];
-        pickH[k] = Hu[s];
+        a.is_seed[s] = 1;
+        a.seeds[a.k] = s;
+        a.pickJ[a.k] = a.Ju[s];
+        a.pickH[a.k] = a.Hu[s];
         c.qsize[0] = 0;
         c.qsize[2] = 0;
         c.qsize[3] = 0;
         c.qsize[1] = (uint32_t)nt;
-        c.stamp[s] = level_id1;
+        c.stamp[s] = a.level_id1;
         c.touched[0] = s;
         *c.ntouched = 1;
-        c.touch_stamp[s] = cascade_id;
+        c.touch_stamp[s] = a.cascade_id;
     }
 }
 
-hipError_t launch_cascade_seed(const GraphDev& g, const int32_t* best, int32_t k, uint8_t* M, int J,
-                               uint8_t* is_seed, int32_t* seeds, uint32_t* pickJ, unsigned long long* pickH,
-                               const uint32_t* Ju, const unsigned long long* Hu, const CascadeDev& c,
-                               uint32_t cascade_id, uint32_t level_id1, hipStream_t st)
+hipError_t launch_cascade_seed(const SeedArgs* args, const Batch& B, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cascade_seed, dim3(1), dim3(64), 0, st, g, best, k, M, J, is_seed, seeds, pickJ, pickH, Ju,
-                       Hu, c, cascade_id, level_id1);
+    hipLaunchKernelGGL(k_cascade_seed, dim3(B.wg0[B.nq]), dim3(64), 0, st, args, B);
     return hipGetLastError();
 }
 
@@ -1079,16 +1092,7 @@ hipError_t launch_cascade_seed(const GraphDev& g, const int32_t* best, int32_t k
 // a contiguous slice of ED, and the (arc, word) items are dealt to lanes.
 // Heads still uncovered where the arc is live get the level-t marker (byte
 // stores) and their out-tasks join Q_{t+1} (once per level, via stamp).
-struct LevelArgs {
-    GraphDev g;
-    const uint32_t* X;
-    int J;
-    uint8_t* M;
-    CascadeDev c;
-    int t;
-    uint32_t level_id;    // stamp of Q_{t+1}
-    uint32_t cascade_id;
-};
+
 
 constexpr int kLevelBufWords = 6 * 64 + 2 * kWaveBufCap;
 
@@ -1107,8 +1111,9 @@ __device__ __forceinline__ int lower_bound_i32(const int* A, int n, int key)
     return lo;
 }
 
-__global__ __launch_bounds__(kWG) void k_cascade_level(LevelArgs a)
+__global__ __launch_bounds__(kWG) void k_cascade_level(const LevelArgs* __restrict__ args, Batch B)
 {
+    IMX_BATCH_PROLOGUE(LevelArgs);
     extern __shared__ uint32_t smem[];
     const int J = a.J;
     const int Jw = J >> 2;
@@ -1127,7 +1132,7 @@ __global__ __launch_bounds__(kWG) void k_cascade_level(LevelArgs a)
     uint32_t* efl = reinterpret_cast<uint32_t*>(est + 64);
     int32_t* qbuf = reinterpret_cast<int32_t*>(efl + 64);
 
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.c.qsize[(a.t + 2) & 3] = 0;
+    if (lb == 0 && threadIdx.x == 0) a.c.qsize[(a.t + 2) & 3] = 0;
     for (int i = threadIdx.x; i < J + kBuckets + 1; i += kWG) sX[i] = a.X[i];
     __syncthreads();
 
@@ -1141,9 +1146,9 @@ __global__ __launch_bounds__(kWG) void k_cascade_level(LevelArgs a)
     const uint32_t mk_cur = marker(a.t);
     const GraphDev& g = a.g;
     const uint32_t* M32 = reinterpret_cast<const uint32_t*>(a.M);
-    const int64_t nw = (int64_t)gridDim.x * kWaves;
+    const int64_t nw = lg * kWaves;
 
-    for (int64_t i = (int64_t)blockIdx.x * kWaves + wave; i < (int64_t)qn; i += nw) {
+    for (int64_t i = lb * kWaves + wave; i < (int64_t)qn; i += nw) {
         const int32_t t = Q[i];
         const int32_t u = g.task_u[t];
         const int64_t e0 = g.task_e0[t];
@@ -1231,40 +1236,55 @@ __global__ __launch_bounds__(kWG) void k_cascade_level(LevelArgs a)
     wl_flush(tlist);
 }
 
-hipError_t launch_cascade_level(const GraphDev& g, const uint32_t* X, int J, uint8_t* M, const CascadeDev& c, int t,
-                                uint32_t level_id, uint32_t cascade_id, hipStream_t st)
+static size_t level_lds(int J)
 {
-    LevelArgs a{g, X, J, M, c, t, level_id, cascade_id};
-    const size_t lds =
-        sizeof(uint32_t) * ((size_t)J + kTableWords + (size_t)kWaves * ((size_t)(J / 2) + kLevelBufWords));
-    static size_t lds_set = 0;
+    return sizeof(uint32_t) * ((size_t)J + kTableWords + (size_t)kWaves * ((size_t)(J / 2) + kLevelBufWords));
+}
+
+hipError_t cascade_level_full_grid(int maxJ, int* grid)
+{
+    static size_t lds_set = 0, attr_set = 0;
     static int per_cu = 0;
+    const size_t lds = level_lds(maxJ);
     if (lds_set != lds) {
-        hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cascade_level),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (err != hipSuccess) return err;
-        err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cascade_level, kWG, lds);
+        if (lds > attr_set) {
+            hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cascade_level),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (err != hipSuccess) return err;
+            attr_set = lds;
+        }
+        hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cascade_level, kWG, lds);
         if (err != hipSuccess) return err;
         if (per_cu < 1) per_cu = 1;
         lds_set = lds;
     }
-    hipLaunchKernelGGL(k_cascade_level, dim3(cu_count() * per_cu), dim3(kWG), lds, st, a);
+    *grid = cu_count() * per_cu;
+    return hipSuccess;
+}
+
+hipError_t launch_cascade_level(const LevelArgs* args, const Batch& B, int maxJ, hipStream_t st)
+{
+    int grid = 0;
+    hipError_t err = cascade_level_full_grid(maxJ, &grid);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k_cascade_level, dim3(B.wg0[B.nq]), dim3(kWG), level_lds(maxJ), st, args, B);
     return hipGetLastError();
 }
 
 // End of a cascade: markers become 0 in every touched row; Ju/Hu of touched
 // rows are recomputed and T grows by the number of newly covered registers.
-__global__ __launch_bounds__(kWG) void k_cascade_finalize(uint8_t* M, int J, uint32_t* Ju, unsigned long long* Hu,
-                                                           CascadeDev c)
+__global__ __launch_bounds__(kWG) void k_cascade_finalize(const FinArgs* __restrict__ args, Batch B)
 {
+    IMX_BATCH_PROLOGUE(FinArgs);
+    const CascadeDev& c = a.c;
     const int lane = lane_id();
-    const int Jw = J >> 2;
+    const int Jw = a.J >> 2;
     const uint32_t nt = *c.ntouched;
-    const int64_t nw = (int64_t)gridDim.x * kWaves;
+    const int64_t nw = lg * kWaves;
     unsigned long long dT = 0;
-    for (int64_t i = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); i < (int64_t)nt; i += nw) {
+    for (int64_t i = lb * kWaves + (threadIdx.x >> 6); i < (int64_t)nt; i += nw) {
         const int32_t v = c.touched[i];
-        uint32_t* row = reinterpret_cast<uint32_t*>(M + (size_t)v * (size_t)J);
+        uint32_t* row = reinterpret_cast<uint32_t*>(a.M + (size_t)v * (size_t)a.J);
         uint32_t cnt = 0;
         unsigned long long h = 0;
         for (int idx = lane; idx < Jw; idx += 64) {
@@ -1285,20 +1305,21 @@ __global__ __launch_bounds__(kWG) void k_cascade_finalize(uint8_t* M, int J, uin
         cnt = wave_sum_u32(cnt);
         h = wave_sum_u64(h);
         if (lane == 0) {
-            const uint32_t old = Ju[v];
-            Ju[v] = cnt;
-            Hu[v] = h;
+            const uint32_t old = a.Ju[v];
+            a.Ju[v] = cnt;
+            a.Hu[v] = h;
             dT += (unsigned long long)(old - cnt);
         }
     }
     if (lane == 0 && dT) atomicAdd(c.T, dT);
 }
 
-hipError_t launch_cascade_finalize(uint8_t* M, int J, uint32_t* Ju, unsigned long long* Hu, const CascadeDev& c,
-                                   hipStream_t st)
+hipError_t launch_cascade_finalize(const FinArgs* args, const Batch& B, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cascade_finalize, dim3(cu_count() * 8), dim3(kWG), 0, st, M, J, Ju, Hu, c);
+    hipLaunchKernelGGL(k_cascade_finalize, dim3(B.wg0[B.nq]), dim3(kWG), 0, st, args, B);
     return hipGetLastError();
 }
+
+int device_cu_count() { return cu_count(); }
 
 }  // namespace imx

@@ -79,3 +79,7 @@ def test_no_silent_cpu_fallback(imx):
     with pytest.raises(imx.IMError) as ei:
         _load(imx, 3, [0, 1, 2, 2], [1, 2], [0.5, 0.5])
     assert ei.value.status == 3
+
+
+def test_footprint_of_null_graph_is_zero(imx):
+    assert imx.lib().im_query_footprint(None, 64, 1) == 0

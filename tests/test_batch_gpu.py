@@ -1,0 +1,164 @@
+"""Batched and continuously admitted queries (engine) against solo runs and the
+oracle: every query's result must be bit-identical alone and in the mix."""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _graphs():
+    return [
+        (graphgen.with_p(graphgen.erdos_renyi(800, 4000, 11), "0.1"), 64, 3, 6),
+        (graphgen.with_p(graphgen.rmat(11, 16, seed=4), "wc"), 256, 5, 8),
+        (graphgen.with_p(graphgen.rmat(10, 8, seed=6), "0.01"), 512, 7, 5),
+        (graphgen.with_p(graphgen.barabasi_albert(2000, 4, seed=2), "wc"), 128, 9, 7),
+        (graphgen.with_p(graphgen.erdos_renyi(300, 1500, 12), "trivalency"), 192, 2, 4),
+        (graphgen.with_p(graphgen.rmat(12, 16, seed=8), "0.1"), 1024, 1, 3),
+    ]
+
+
+def _solo(imx, G, J, seed, K):
+    S = imx.Sketch(G, J, seed)
+    r = S.select(K)
+    S.free()
+    return r
+
+
+def _same(a, b):
+    assert list(a["seeds"]) == list(b["seeds"])
+    assert list(a["T"]) == list(b["T"])
+    assert a["est"].tobytes() == b["est"].tobytes()
+    assert a["spread"] == b["spread"]
+    assert a["stats"]["rebuilds"] == b["stats"]["rebuilds"]
+
+
+def test_engine_mix_equals_solo(imx, orc):
+    cases = _graphs()
+    Gs = [imx.Graph.from_graphgen(g) for g, *_ in cases]
+    solo = [_solo(imx, G, J, s, K) for G, (_, J, s, K) in zip(Gs, cases)]
+    # first two against the oracle as well
+    for (g, J, s, K), r in list(zip(cases, solo))[:2]:
+        ref = orc.greedy(g, J, s, K, keep_registers=False)
+        assert list(r["seeds"]) == list(ref["seeds"]) and list(r["T"]) == list(ref["T"])
+    E = imx.Engine(max_queries=16)
+    ids = [E.submit(G, J, s, K) for G, (_, J, s, K) in zip(Gs, cases)]
+    _say(f"[engine] {len(ids)} queries")
+    res = E.run()
+    for qid, r in zip(ids, solo):
+        _same(res[qid], r)
+    E.free()
+
+
+def test_engine_continuous_admission(imx):
+    """Queries submitted while others are half-way produce the same results."""
+    cases = _graphs()
+    Gs = [imx.Graph.from_graphgen(g) for g, *_ in cases]
+    solo = [_solo(imx, G, J, s, K) for G, (_, J, s, K) in zip(Gs, cases)]
+    E = imx.Engine(max_queries=4)
+    pending = list(range(len(cases)))
+    ids = {}
+    results = {}
+    steps = 0
+    while pending or E.info()["queries"]:
+        # admit one new query every few steps while slots are free
+        if pending and steps % 3 == 0:
+            i = pending[0]
+            G, (_, J, s, K) = Gs[i], cases[i]
+            try:
+                ids[E.submit(G, J, s, K)] = i
+                pending.pop(0)
+            except imx.IMError as e:
+                assert e.status == 2
+        E.step()
+        steps += 1
+        for qid in E.poll():
+            results[ids[qid]] = E.result(qid)
+        assert steps < 100000
+    for i, r in enumerate(solo):
+        _same(results[i], r)
+    E.free()
+
+
+def test_engine_budget_admission(imx):
+    g = graphgen.with_p(graphgen.rmat(11, 16, seed=2), "0.1")
+    G = imx.Graph.from_graphgen(g)
+    need = imx.im_query_footprint(G.handle, 256, 5)
+    assert need > 256 * g.n
+    E = imx.Engine(max_queries=8, hbm_budget_bytes=2 * need + need // 2)
+    a = E.submit(G, 256, 1, 5)
+    b = E.submit(G, 256, 2, 5)
+    with pytest.raises(imx.IMError) as ei:
+        E.submit(G, 256, 3, 5)
+    assert ei.value.status == 2
+    assert E.info()["bytes_used"] <= E.info()["bytes_budget"]
+    res = E.run()
+    assert set(res) == {a, b}
+    c = E.submit(G, 256, 3, 5)  # memory released by the collected results
+    res2 = E.run()
+    solo = _solo(imx, G, 256, 3, 5)
+    _same(res2[c], solo)
+    E.free()
+
+
+def test_select_seeds_batch_api(imx):
+    cases = _graphs()[:4]
+    Gs = [imx.Graph.from_graphgen(g) for g, *_ in cases]
+    seeds, spread = imx.im_select_seeds_batch(Gs, [c[1] for c in cases], [c[2] for c in cases],
+                                              [c[3] for c in cases])
+    for G, (_, J, s, K), sd, sp in zip(Gs, cases, seeds, spread):
+        r = _solo(imx, G, J, s, K)
+        assert list(sd) == list(r["seeds"]) and sp == r["spread"]
+
+
+def test_engine_many_queries_one_graph(imx):
+    """More queries than one launch holds (64) on one graph, different seeds."""
+    g = graphgen.with_p(graphgen.erdos_renyi(400, 2000, 5), "0.2")
+    G = imx.Graph.from_graphgen(g)
+    E = imx.Engine(max_queries=80)
+    ids = [E.submit(G, 64, s, 3) for s in range(70)]
+    res = E.run()
+    for s in (0, 33, 69):
+        _same(res[ids[s]], _solo(imx, G, 64, s, 3))
+    E.free()
+
+
+def test_server_results_equal_solo(imx):
+    """Continuous batching under a bursty arrival trace: every served result is
+    identical to the query run alone."""
+    from paper_2410_14047_amd import serve
+    base = graphgen.rmat(11, 16, seed=3)
+    graphs = {"r11_0.01": imx.Graph.from_graphgen(graphgen.with_p(base, "0.01")),
+              "r11_wc": imx.Graph.from_graphgen(graphgen.with_p(base, "wc")),
+              "er": imx.Graph.from_graphgen(graphgen.with_p(graphgen.erdos_renyi(600, 3000, 2), "0.1"))}
+    rng = np.random.default_rng(5)
+    names = sorted(graphs)
+    trace, t = [], 0.0
+    for i in range(24):
+        t += float(rng.exponential(0.002))
+        trace.append((t, names[i % 3], int(rng.choice([64, 256])), int(i), int(rng.integers(2, 8))))
+    srv = serve.Server(graphs, max_queries=6).start()
+    res, makespan = serve.replay(srv, trace)
+    srv.stop()
+    summ = serve.latency_summary(res, makespan)
+    _say(f"[serve] {summ}")
+    for (ta, gname, J, seed, K), r in zip(trace, res):
+        _same(r, _solo(imx, graphs[gname], J, seed, K))
+
+
+def test_autotune_keeps_outputs(imx):
+    from paper_2410_14047_amd import autotune
+    g = graphgen.with_p(graphgen.rmat(11, 16, seed=9), "wc")
+    G = imx.Graph.from_graphgen(g)
+    qs = [(G, 256, s, 4) for s in range(3)]
+    cands = [dict(group_first=64, group_rest=16, rounds_per_step=2, dense_div=16),
+             dict(group_first=32, group_rest=64, rounds_per_step=4, dense_div=8)]
+    out = autotune.autotune(qs, candidates=cands)
+    assert out["best"] in cands and len(out["table"]) == 2
