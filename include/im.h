@@ -194,12 +194,13 @@ im_status im_engine_create(int32_t max_queries, uint64_t hbm_budget_bytes, void*
 /* Scheduling parameters of an engine (they change speed, never results):
  *   group_first, group_rest  lanes per propagation task (16, 32 or 64) in the
  *                            first sweep after a fill and in later sweeps;
- *   rounds_per_step          sweeps / cascade levels launched per step (1..4);
+ *   rounds_per_step          sweeps / cascade levels launched per step (1..16);
  *   dense_div                a sweep visits every task instead of an active
  *                            list when more than n / dense_div rows changed in
  *                            the previous sweep (>= 1).
- * Defaults: 64, 64, 4, 16 (environment IMX_GROUP_FIRST / IMX_GROUP override
- * the group sizes). */
+ * Defaults: 64, 64, 8, 16; the environment variables IMX_GROUP_FIRST,
+ * IMX_GROUP, IMX_ROUNDS and IMX_DENSE_DIV override them at engine creation
+ * (an out-of-range value makes creation fail with IM_EINVAL). */
 typedef struct im_tuning {
     int32_t group_first;
     int32_t group_rest;

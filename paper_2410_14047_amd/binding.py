@@ -324,7 +324,7 @@ class Engine:
         del self._K[qid]
         return dict(seeds=seeds, spread=spread.value, est=est, T=T, stats=stats.as_dict())
 
-    def set_tuning(self, group_first: int = 64, group_rest: int = 64, rounds_per_step: int = 4,
+    def set_tuning(self, group_first: int = 64, group_rest: int = 64, rounds_per_step: int = 8,
                    dense_div: int = 16) -> None:
         t = im_tuning(group_first, group_rest, rounds_per_step, dense_div)
         _check(lib().im_engine_set_tuning(self.handle, ctypes.byref(t)))

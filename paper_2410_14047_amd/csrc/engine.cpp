@@ -20,7 +20,9 @@
 namespace imx {
 namespace {
 
-constexpr int kMaxRounds = 4;  // sweeps / cascade levels per tick at most (the counter rings hold 4)
+// Sweeps / cascade levels per tick at most.  Convergence and the end of a
+// cascade are detected on the device; launches past them return at once.
+constexpr int kMaxRounds = 16;
 
 // Per-query counters the host reads back every tick (one array per engine).
 struct SlotStatus {
@@ -31,11 +33,13 @@ struct SlotStatus {
     uint32_t chg_count[4];
     uint32_t dense[4];
     uint32_t ntouched;
-    uint32_t pad[5];
+    uint32_t conv;       // first sweep of the build that changed nothing (~0u: none yet)
+    uint32_t level_end;  // first empty level of the cascade (~0u: running)
+    uint32_t pad[3];
 };
 static_assert(sizeof(SlotStatus) == 128, "status record size");
 
-enum class Stage { Fill, Sweeps, Estimate, Pick, Levels, Finalize, Built, Done, Failed };
+enum class Stage { Fill, Sweeps, Estimate, Pick, Levels, Built, Done, Failed };
 
 double now_ms()
 {
@@ -72,10 +76,9 @@ struct Query {
     bool fresh = true;      // the next fill is the sketch's first: every register uncovered
     bool need_est = false;  // the next pick must recompute the estimate terms (after a build)
     int sweep = 0;
-    int build_sweeps = 0;
     int level = 1;
     int k = 0;
-    uint32_t cascade_id = 0, level_base = 0;
+    uint32_t cascade_id = 0;
     uint64_t T_old = 0;
     std::vector<uint64_t> T;
     im_stats st{};
@@ -105,14 +108,23 @@ public:
         IMX_HIP(hipMalloc(&status_dev_, sizeof(SlotStatus) * cap_));
         IMX_HIP(hipMemsetAsync(status_dev_, 0, sizeof(SlotStatus) * cap_, st_));
         IMX_HIP(hipHostMalloc(reinterpret_cast<void**>(&status_host_), sizeof(SlotStatus) * cap_, 0));
-        args_cap_ = (size_t)cap_ * 8192 + (1u << 16);
+        // argument records of one tick: at most kMaxRounds x (prep, propagate,
+        // mark) or kMaxRounds x (level, compaction) plus a few per query, and
+        // one 256-byte alignment per launch
+        static_assert(sizeof(PrepArgs) + sizeof(PropArgs) + sizeof(MarkArgs) <= 3 * 256, "sweep records");
+        static_assert(sizeof(LevelArgs) + sizeof(LevelCompactArgs) <= 3 * 256, "level records");
+        const size_t chunks = ((size_t)cap_ + kMaxBatch - 1) / kMaxBatch;
+        args_cap_ = (size_t)cap_ * (kMaxRounds * 3 * 256 + 2048) + chunks * (kMaxRounds * 5 + 16) * 256;
         IMX_HIP(hipMalloc(&args_dev_, args_cap_));
         IMX_HIP(hipHostMalloc(reinterpret_cast<void**>(&args_host_), args_cap_, 0));
         for (auto& e : ev_) IMX_HIP(hipEventCreate(&e));
-        const char* a = std::getenv("IMX_GROUP_FIRST");
-        const char* b = std::getenv("IMX_GROUP");
-        if (a) tune_.group_first = std::atoi(a);
-        if (b) tune_.group_rest = std::atoi(b);
+        // Environment overrides of the default tuning (validated like im_engine_set_tuning).
+        im_tuning t = tune_;
+        if (const char* v = std::getenv("IMX_GROUP_FIRST")) t.group_first = std::atoi(v);
+        if (const char* v = std::getenv("IMX_GROUP")) t.group_rest = std::atoi(v);
+        if (const char* v = std::getenv("IMX_ROUNDS")) t.rounds_per_step = std::atoi(v);
+        if (const char* v = std::getenv("IMX_DENSE_DIV")) t.dense_div = std::atoi(v);
+        if (set_tuning(t) != IM_OK) return IM_EINVAL;
         IMX_HIP(hipStreamSynchronize(st_));
         return IM_OK;
     }
@@ -132,7 +144,8 @@ public:
     {
         const size_t n = (size_t)g->n, nt = (size_t)std::max<int64_t>(g->ntasks, 1);
         const size_t nit = (size_t)std::max<int64_t>(g->n_in_tasks, 1), bmw = (n + 31) / 32;
-        return n * (size_t)J + n * (4 + 8 + 1 + 4 * 3) + bmw * 12 + nt * 16 + nit * 4 + ((size_t)J + kTableWords) * 4 +
+        return n * (size_t)J + n * (4 + 8 + 1 + 4 * 2) + (size_t)flag_bytes((int64_t)n) * 2 + bmw * 8 + nt * 16 +
+               nit * 4 + ((size_t)J + kTableWords) * 4 +
                (size_t)kArgmaxBlocks * 16 + (size_t)std::max(K, 1) * 16 + 4096;
     }
 
@@ -168,10 +181,10 @@ public:
         const size_t nt = (size_t)std::max<int64_t>(g->ntasks, 1), nit = (size_t)std::max<int64_t>(g->n_in_tasks, 1);
         Arena& A = q->arena;
         if (A.alloc(&q->M, nJ) || A.alloc(&q->X, (size_t)J + kTableWords) || A.alloc(&q->Ju, n) || A.alloc(&q->Hu, n) ||
-            A.alloc(&q->sw.chg[0], bmw) || A.alloc(&q->sw.chg[1], bmw) || A.alloc(&q->sw.act_bm, bmw) ||
+            A.alloc(&q->sw.chg[0], bmw) || A.alloc(&q->sw.chg[1], bmw) || A.alloc(&q->sw.act8, flag_bytes(n)) ||
             A.alloc(&q->sw.act_tasks[0], nt) || A.alloc(&q->sw.act_tasks[1], nt) || A.alloc(&q->sw.chg_list, nit) ||
             A.alloc(&q->is_seed, n) || A.alloc(&q->best, 1) || A.alloc(&q->c.q[0], nt) || A.alloc(&q->c.q[1], nt) ||
-            A.alloc(&q->c.stamp, n) || A.alloc(&q->c.touched, n) || A.alloc(&q->c.touch_stamp, n) ||
+            A.alloc(&q->c.lv8, flag_bytes(n)) || A.alloc(&q->c.touched, n) || A.alloc(&q->c.touch_stamp, n) ||
             A.alloc(&q->am.pJ, kArgmaxBlocks) || A.alloc(&q->am.pH, kArgmaxBlocks) || A.alloc(&q->am.pid, kArgmaxBlocks)) {
             A.release();
             return set_error(IM_ENOMEM, "device allocation failed");
@@ -189,13 +202,16 @@ public:
         q->sw.act_count = S->act_count;
         q->sw.chg_count = S->chg_count;
         q->sw.dense = S->dense;
+        q->sw.conv = &S->conv;
+        q->c.level_end = &S->level_end;
         q->c.qsize = S->qsize;
         q->c.T = &S->T;
         q->c.ntouched = &S->ntouched;
 
         hipError_t e = hipMemsetAsync(S, 0, sizeof(SlotStatus), st_);
         if (e == hipSuccess) e = hipMemsetAsync(q->is_seed, 0, n, st_);
-        if (e == hipSuccess) e = hipMemsetAsync(q->c.stamp, 0, sizeof(uint32_t) * n, st_);
+        if (e == hipSuccess) e = hipMemsetAsync(q->sw.act8, 0, flag_bytes(n), st_);
+        if (e == hipSuccess) e = hipMemsetAsync(q->c.lv8, 0, flag_bytes(n), st_);
         if (e == hipSuccess) e = hipMemsetAsync(q->c.touch_stamp, 0, sizeof(uint32_t) * n, st_);
         if (e == hipSuccess && q->pc) e = hipMemsetAsync(q->pc, 0, sizeof(PropCounters), st_);
         if (e == hipSuccess) e = launch_sim_values(seed, J, q->X, st_);
@@ -361,7 +377,7 @@ private:
     uint8_t* args_host_ = nullptr;
     size_t args_cap_ = 0, args_off_ = 0;
     hipEvent_t ev_[2 * kMaxRounds] = {};
-    im_tuning tune_{64, 64, 4, 16};
+    im_tuning tune_{64, 64, 8, 16};
 };
 
 im_status Engine::step()
@@ -369,7 +385,7 @@ im_status Engine::step()
     std::vector<Query*> act;
     for (Query* q : slots_)
         if (q && (q->stage == Stage::Fill || q->stage == Stage::Sweeps || q->stage == Stage::Estimate ||
-                  q->stage == Stage::Pick || q->stage == Stage::Levels || q->stage == Stage::Finalize))
+                  q->stage == Stage::Pick || q->stage == Stage::Levels))
             act.push_back(q);
     if (act.empty()) return IM_OK;
     const int cus = device_cu_count();
@@ -384,7 +400,7 @@ im_status Engine::step()
             out.emplace_back(v.begin() + i, v.begin() + std::min(v.size(), i + kMaxBatch));
         return out;
     };
-    std::vector<Query*> fill_q, sweep_q, est_q, pick_q, level_q, fin_q;
+    std::vector<Query*> fill_q, sweep_q, est_q, pick_q, level_q;
     for (Query* q : act) {
         switch (q->stage) {
         case Stage::Fill: fill_q.push_back(q); sweep_q.push_back(q); break;
@@ -395,7 +411,6 @@ im_status Engine::step()
             level_q.push_back(q);
             break;
         case Stage::Levels: level_q.push_back(q); break;
-        case Stage::Finalize: fin_q.push_back(q); break;
         default: break;
         }
     }
@@ -410,7 +425,8 @@ im_status Engine::step()
         Launch<FillArgs> L;
         for (Query* q : ch) {
             L.args.push_back(FillArgs{q->M, q->g->n, q->J, q->fresh ? 1 : 0, q->seed});
-            L.want.push_back(std::min<int64_t>(16384, (q->g->n * (q->J / 4) + 2047) / 2048));
+            const int64_t rows_per_wg = 256 / row_lanes(q->J);
+            L.want.push_back(std::min<int64_t>(cus * 16, (q->g->n + rows_per_wg - 1) / rows_per_wg));
         }
         L_fill.push_back(std::move(L));
     }
@@ -436,8 +452,8 @@ im_status Engine::step()
                 const int s = q->sweep + b;
                 const GraphDev gd = q->g->dev();
                 const int64_t nwords = (q->g->n + 31) / 32;
-                P.args.push_back(PrepArgs{q->sw, nwords, s});
-                P.want.push_back(std::min<int64_t>(256, (nwords + 255) / 256));
+                P.args.push_back(PrepArgs{q->sw, q->g->task_start, q->g->n, nwords, s});
+                P.want.push_back(std::min<int64_t>(cus * 4, (q->g->n + 16 * kWG - 1) / (16 * kWG)));
                 PropArgs pa{gd,
                             q->X,
                             q->J,
@@ -449,6 +465,7 @@ im_status Engine::step()
                             q->sw.chg_list,
                             &q->sw.chg_count[s & 3],
                             &q->sw.dense[s & 3],
+                            q->sw.conv,
                             &q->sw.rows_changed[s & 3],
                             q->pc};
                 Launch<PropArgs>& T = (s == 0) ? F : R;
@@ -473,7 +490,8 @@ im_status Engine::step()
         Launch<EstArgs> L;
         for (Query* q : ch) {
             L.args.push_back(EstArgs{q->M, q->g->n, q->J, q->Ju, q->Hu});
-            L.want.push_back(std::min<int64_t>(65536, (q->g->n + kWaves - 1) / kWaves));
+            const int64_t rows_per_wg = kWG / row_lanes(q->J);
+            L.want.push_back(std::min<int64_t>(cus * 16, (q->g->n + rows_per_wg - 1) / rows_per_wg));
         }
         L_est.push_back(std::move(L));
     }
@@ -487,13 +505,14 @@ im_status Engine::step()
             L.args.push_back(ArgmaxArgs{q->Ju, q->Hu, q->is_seed, q->g->n, q->am, q->best, std::max(nparts, 1)});
             L.want.push_back(std::max(nparts, 1));
             S.args.push_back(SeedArgs{q->g->dev(), q->best, q->k, q->M, q->J, q->is_seed, q->seeds, q->pickJ, q->pickH,
-                                      q->Ju, q->Hu, q->c, q->cascade_id, q->level_base + 1});
+                                      q->Ju, q->Hu, q->c, q->cascade_id});
             S.want.push_back(1);
         }
         L_am.push_back(std::move(L));
         L_seed.push_back(std::move(S));
     }
     std::vector<std::vector<Launch<LevelArgs>>> L_lvl(level_q.empty() ? 0 : nr);
+    std::vector<std::vector<Launch<LevelCompactArgs>>> L_cmp(level_q.empty() ? 0 : nr);
     int full_level = 0;
     if (!level_q.empty()) {
         int maxJ = 0;
@@ -503,17 +522,20 @@ im_status Engine::step()
     for (int b = 0; b < (int)L_lvl.size(); ++b)
         for (auto& ch : chunks(level_q)) {
             Launch<LevelArgs> L;
+            Launch<LevelCompactArgs> C;
             for (Query* q : ch) {
                 const int t = q->level + b;
-                L.args.push_back(LevelArgs{q->g->dev(), q->X, q->J, q->M, q->c, t, q->level_base + (uint32_t)t + 1,
-                                           q->cascade_id});
+                L.args.push_back(LevelArgs{q->g->dev(), q->X, q->J, q->M, q->c, t});
                 L.want.push_back((q->g->ntasks + kWaves - 1) / kWaves);
                 L.maxJ = std::max(L.maxJ, q->J);
+                C.args.push_back(LevelCompactArgs{q->g->task_start, q->g->n, q->c, t, q->cascade_id});
+                C.want.push_back(std::min<int64_t>(cus * 4, (q->g->n + 16 * kWG - 1) / (16 * kWG)));
             }
             L_lvl[b].push_back(std::move(L));
+            L_cmp[b].push_back(std::move(C));
         }
     std::vector<Launch<FinArgs>> L_fin;
-    for (auto& ch : chunks(fin_q)) {
+    for (auto& ch : chunks(level_q)) {  // each runs only once its cascade has ended
         Launch<FinArgs> L;
         for (Query* q : ch) {
             L.args.push_back(FinArgs{q->M, q->J, q->Ju, q->Hu, q->c});
@@ -541,6 +563,8 @@ im_status Engine::step()
     for (auto& L : L_seed) ok &= finish(L, 0);
     for (auto& R : L_lvl)
         for (auto& L : R) ok &= finish(L, full_level);
+    for (auto& R : L_cmp)
+        for (auto& L : R) ok &= finish(L, 0);
     for (auto& L : L_fin) ok &= finish(L, 0);
     if (!ok) return set_error(IM_EINVAL, "too many queries for one tick's argument buffer");
     IMX_HIP(hipMemcpyAsync(args_dev_, args_host_, args_off_, hipMemcpyHostToDevice, st_));
@@ -566,8 +590,10 @@ im_status Engine::step()
         IMX_HIP(launch_argmax(L_am[i].dev, L_am[i].B, fin, st_));
         IMX_HIP(launch_cascade_seed(L_seed[i].dev, L_seed[i].B, st_));
     }
-    for (auto& R : L_lvl)
-        for (auto& L : R) IMX_HIP(launch_cascade_level(L.dev, L.B, L.maxJ, st_));
+    for (size_t b = 0; b < L_lvl.size(); ++b) {
+        for (auto& L : L_lvl[b]) IMX_HIP(launch_cascade_level(L.dev, L.B, L.maxJ, st_));
+        for (auto& L : L_cmp[b]) IMX_HIP(launch_cascade_compact(L.dev, L.B, st_));
+    }
     for (auto& L : L_fin) IMX_HIP(launch_cascade_finalize(L.dev, L.B, st_));
     IMX_HIP(hipMemcpyAsync(status_host_, status_dev_, sizeof(SlotStatus) * cap_, hipMemcpyDeviceToHost, st_));
     IMX_HIP(hipStreamSynchronize(st_));
@@ -587,25 +613,20 @@ im_status Engine::step()
         case Stage::Sweeps: {
             q->st.prop_kernel_ms += prop_ms / (double)sweep_q.size();
             q->st.prop_launches += nr;
-            bool done = false;
-            for (int b = 0; b < nr && !done; ++b) {
-                ++q->build_sweeps;
-                if (S.rows_changed[(q->sweep + b) & 3] == 0) done = true;
-            }
             q->sweep += nr;
-            if (done) {
-                q->st.total_sweeps += q->build_sweeps;
+            if (S.conv != ~0u) {  // sweep S.conv (0-based) changed nothing: the build is complete
+                const int sweeps = (int)S.conv + 1;
+                q->st.total_sweeps += sweeps;
                 if (q->fresh) {
-                    q->st.build_sweeps = q->build_sweeps;
+                    q->st.build_sweeps = sweeps;
                     q->st.build_ms = now_ms() - q->t_build0;
                     q->t_sel0 = now_ms();
                 }
                 q->fresh = false;
-                q->build_sweeps = 0;
                 q->sweep = 0;
                 q->need_est = true;
                 q->stage = q->park ? Stage::Estimate : Stage::Pick;
-            } else if (q->build_sweeps > q->g->n + 2) {
+            } else if (q->sweep > q->g->n + 2) {
                 q->stage = Stage::Failed;
                 return set_error(IM_EDEVICE, "propagation did not converge");
             } else {
@@ -622,32 +643,27 @@ im_status Engine::step()
         case Stage::Levels: {
             q->need_est = false;
             q->level += nr;
-            q->st.cascade_levels += nr;
-            if (S.qsize[q->level & 3] == 0) {
-                q->stage = Stage::Finalize;
-                q->level_base += (uint32_t)q->level + 2;
+            if (S.level_end != ~0u) {  // the cascade ended and was finalized in this tick
+                q->st.cascade_levels += S.level_end - 1u;
+                const uint64_t T = S.T;
+                q->T[q->k] = T;
+                ++q->k;
+                if (q->k >= q->K) {
+                    q->stage = Stage::Done;
+                    q->st.select_ms = now_ms() - q->t_sel0;
+                } else if (100 * (T - q->T_old) > T) {
+                    q->T_old = T;
+                    ++q->st.rebuilds;
+                    q->stage = Stage::Fill;
+                    q->sweep = 0;
+                } else {
+                    q->stage = Stage::Pick;
+                }
             } else if (q->level > q->g->n + 8) {
                 q->stage = Stage::Failed;
                 return set_error(IM_EDEVICE, "cascade did not terminate");
             } else {
                 q->stage = Stage::Levels;
-            }
-            break;
-        }
-        case Stage::Finalize: {
-            const uint64_t T = S.T;
-            q->T[q->k] = T;
-            ++q->k;
-            if (q->k >= q->K) {
-                q->stage = Stage::Done;
-                q->st.select_ms = now_ms() - q->t_sel0;
-            } else if (100 * (T - q->T_old) > T) {
-                q->T_old = T;
-                ++q->st.rebuilds;
-                q->stage = Stage::Fill;
-                q->sweep = 0;
-            } else {
-                q->stage = Stage::Pick;
             }
             break;
         }

@@ -47,28 +47,48 @@ struct GraphDev {
 // changed in sweep s-1) and the active task list act_tasks[s&1] (count
 // act_count[s&3]); it writes chg[(s+1)&1], the in-tasks of its changed rows
 // (chg_list, count chg_count[s&3]) and rows_changed[s&3].  The mark step of
-// sweep s turns chg_list into act_tasks[(s+1)&1] / act_count[(s+1)&3].
+// sweep s flags the sources of those in-arcs in act8 (plain byte stores), and
+// the prep step of sweep s+1 compacts the flags into act_tasks[(s+1)&1] /
+// act_count[(s+1)&3], clearing them.
 struct SweepDev {
     int32_t* act_tasks[2];            // [ntasks] each
     uint32_t* act_count;              // [4]
     uint32_t* chg[2];                 // [ceil(n/32)] each
-    uint32_t* act_bm;                 // [ceil(n/32)] vertices already activated
+    uint8_t* act8;                    // [flag_bytes(n)] vertex activated for the next sweep; all 0 between sweeps
     int32_t* chg_list;                // [n_in_tasks]
     uint32_t* chg_count;              // [4]
     unsigned long long* rows_changed; // [4]
     uint32_t* dense;                  // [4] sweep s visits every task when dense[s&3] != 0
+    uint32_t* conv;                   // first sweep of the build that changed no row (~0u: none yet);
+                                      // kernels of later sweeps return at once
 };
 
 // Device state of the covering cascade (union-frontier BFS over tasks).
+// Level t flags the vertices it newly covers in lv8 (plain byte stores); the
+// compaction after level t turns the flags into frontier Q_{t+1} and the
+// touched list, clearing them.
 struct CascadeDev {
     int32_t* q[2];           // frontier out-task lists, capacity ntasks each
     uint32_t* qsize;         // ring of 4 list-size counters
-    uint32_t* stamp;         // [n] id of the last frontier v was appended to
+    uint8_t* lv8;            // [flag_bytes(n)] covered at the current level; all 0 between levels
     int32_t* touched;        // [n] distinct vertices touched by this cascade
     uint32_t* ntouched;      // counter for `touched`
     uint32_t* touch_stamp;   // [n] id of the last cascade that touched v
     unsigned long long* T;   // covered (vertex, simulation) pairs
+    uint32_t* level_end;     // first level of the cascade with an empty frontier (~0u: running)
 };
+
+// Row-streaming kernels (fill, estimate) give each row an aligned group of L
+// lanes, L the largest power of two not above min(64, J/16); each lane owns
+// 16-byte chunks (16 registers) of the row, strided by L.
+__host__ __device__ inline int row_lanes(int J)
+{
+    const int c = J / 16;
+    return (c >= 64) ? 64 : (c >= 32) ? 32 : (c >= 16) ? 16 : (c >= 8) ? 8 : 4;
+}
+
+// Per-vertex flag arrays are padded to whole 16-byte chunks.
+inline int64_t flag_bytes(int64_t n) { return (n + 15) / 16 * 16; }
 
 // Event counts of the instrumented propagation kernel (algorithmic traffic).
 struct PropCounters {
@@ -108,6 +128,8 @@ struct FillArgs {
 
 struct PrepArgs {
     SweepDev s;
+    const int32_t* task_start;  // [n+1] out-tasks of each vertex
+    int64_t n;
     int64_t nwords;
     int sweep;
 };
@@ -124,6 +146,7 @@ struct PropArgs {
     int32_t* chg_list;
     uint32_t* chg_count;
     const uint32_t* dense;        // nonzero: visit every task this sweep
+    const uint32_t* conv;         // the build converged before this sweep when != ~0u
     unsigned long long* rows_changed;
     PropCounters* stats;          // instrumented variant only
 };
@@ -167,7 +190,6 @@ struct SeedArgs {
     const unsigned long long* Hu;
     CascadeDev c;
     uint32_t cascade_id;
-    uint32_t level_id1;
 };
 
 struct LevelArgs {
@@ -177,7 +199,13 @@ struct LevelArgs {
     uint8_t* M;
     CascadeDev c;
     int t;
-    uint32_t level_id;    // stamp of Q_{t+1}
+};
+
+struct LevelCompactArgs {
+    const int32_t* task_start;  // [n+1]
+    int64_t n;
+    CascadeDev c;
+    int t;                // the level whose flags are compacted into Q_{t+1}
     uint32_t cascade_id;
 };
 
@@ -205,6 +233,7 @@ hipError_t launch_estimate(const EstArgs* args, const Batch& B, hipStream_t st);
 hipError_t launch_argmax(const ArgmaxArgs* args, const Batch& partial, const Batch& final_, hipStream_t st);
 hipError_t launch_cascade_seed(const SeedArgs* args, const Batch& B, hipStream_t st);
 hipError_t launch_cascade_level(const LevelArgs* args, const Batch& B, int maxJ, hipStream_t st);
+hipError_t launch_cascade_compact(const LevelCompactArgs* args, const Batch& B, hipStream_t st);
 hipError_t launch_cascade_finalize(const FinArgs* args, const Batch& B, hipStream_t st);
 
 }  // namespace imx

@@ -260,6 +260,127 @@ __device__ __forceinline__ void wl_append_uniform(WaveList& w, int cnt, int32_t 
     w.n += cnt;
 }
 
+// End-of-kernel flush of the lists of every wave of the workgroup with one
+// global atomic per workgroup (same-address atomics serialise at memory, so
+// per-wave flushes of thousands of waves dominate short kernels).  Every
+// thread of the workgroup must call it; all waves' lists share L and ctr.
+// `tmp` is kWaves + 1 words of LDS.
+__device__ __forceinline__ void wg_flush(WaveList& w, uint32_t* tmp)
+{
+    const int wave = (int)(threadIdx.x >> 6);
+    const int lane = lane_id();
+    if (lane == 0) tmp[wave] = (uint32_t)w.n;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tot = 0;
+        for (int i = 0; i < kWaves; ++i) tot += tmp[i];
+        tmp[kWaves] = tot ? atomicAdd(w.ctr, tot) : 0u;
+    }
+    __syncthreads();
+    uint32_t base = tmp[kWaves];
+    for (int i = 0; i < wave; ++i) base += tmp[i];
+    for (int i = lane; i < w.n; i += 64) w.L[base + i] = w.buf[i];
+    w.n = 0;
+    __syncthreads();
+}
+
+// Sum of a per-wave 64-bit count over the workgroup, added to *ctr with one
+// atomic (every thread must call; `tmp` is kWaves 64-bit words of LDS).
+__device__ __forceinline__ void wg_add_u64(unsigned long long x, unsigned long long* ctr, unsigned long long* tmp)
+{
+    const int wave = (int)(threadIdx.x >> 6);
+    x = wave_sum_u64(x);
+    if (lane_id() == 0) tmp[wave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long tot = 0;
+        for (int i = 0; i < kWaves; ++i) tot += tmp[i];
+        if (tot) atomicAdd(ctr, tot);
+    }
+    __syncthreads();
+}
+
+// Compaction of a per-vertex flag array (flag_bytes(n) bytes, 16 flags per
+// lane): every flagged vertex v appends its out-tasks task_start[v] ..
+// task_start[v+1]-1 to L and, with TOUCH, appends v itself to T unless
+// touch_stamp[v] already holds `id` (then sets it).  The flags are cleared.
+// Every vertex belongs to one lane, so flags and stamps need no atomics; the
+// lists take one atomic per staged batch.  Wave-uniform control flow.
+template <bool TOUCH>
+__device__ __forceinline__ void compact_flags(uint8_t* flags, int64_t n, const int32_t* task_start, WaveList& L,
+                                              WaveList& T, uint32_t* touch_stamp, uint32_t id, int64_t first_wave,
+                                              int64_t nwaves)
+{
+    const int lane = lane_id();
+    const int64_t nchunks = (n + 15) / 16;
+    uint4* F = reinterpret_cast<uint4*>(flags);
+    for (int64_t cb = first_wave * 64; cb < nchunks; cb += nwaves * 64) {
+        const int64_t c = cb + lane;
+        uint4 f = make_uint4(0u, 0u, 0u, 0u);
+        if (c < nchunks) f = F[c];
+        const bool any = (f.x | f.y | f.z | f.w) != 0u;
+        if (__ballot(any) == 0ull) continue;
+        // task ranges (and stamps) of the chunk's 16 vertices, loaded at once
+        int32_t ts[17];
+        uint32_t st[16];
+#pragma unroll
+        for (int b = 0; b < 17; ++b) ts[b] = 0;
+#pragma unroll
+        for (int b = 0; b < 16; ++b) st[b] = id;
+        const int64_t v0 = c * 16;
+        if (any) {
+            F[c] = make_uint4(0u, 0u, 0u, 0u);
+            if (v0 + 16 <= n) {
+                const int4* p = reinterpret_cast<const int4*>(task_start + v0);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int4 q = p[k];
+                    ts[4 * k] = q.x;
+                    ts[4 * k + 1] = q.y;
+                    ts[4 * k + 2] = q.z;
+                    ts[4 * k + 3] = q.w;
+                }
+                ts[16] = task_start[v0 + 16];
+                if (TOUCH) {
+                    const uint4* ps = reinterpret_cast<const uint4*>(touch_stamp + v0);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const uint4 q = ps[k];
+                        st[4 * k] = q.x;
+                        st[4 * k + 1] = q.y;
+                        st[4 * k + 2] = q.z;
+                        st[4 * k + 3] = q.w;
+                    }
+                }
+            } else {  // the last, partial chunk
+#pragma unroll
+                for (int b = 0; b < 17; ++b)
+                    if (v0 + b <= n) ts[b] = task_start[v0 + b];
+                if (TOUCH) {
+#pragma unroll
+                    for (int b = 0; b < 16; ++b)
+                        if (v0 + b < n) st[b] = touch_stamp[v0 + b];
+                }
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < 16; ++b) {
+            const uint32_t fw = (b < 4) ? f.x : (b < 8) ? f.y : (b < 12) ? f.z : f.w;
+            const bool set = ((fw >> (8 * (b & 3))) & 0xffu) != 0u;
+            if (__ballot(set) == 0ull) continue;
+            const int32_t v = (int32_t)(v0 + b);
+            const int cnt = set ? ts[b + 1] - ts[b] : 0;
+            bool push = false;
+            if (TOUCH && set && st[b] != id) {
+                touch_stamp[v] = id;
+                push = true;
+            }
+            wl_append_ranges(L, cnt, ts[b]);
+            if (TOUCH) wl_append_ranges(T, push ? 1 : 0, v);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Batched launches: the workgroups of one launch are split among up to
 // kMaxBatch queries (query i owns workgroups wg0[i] .. wg0[i+1]-1 and reads
@@ -277,7 +398,7 @@ __device__ __forceinline__ int batch_index(const Batch& B)
 
 #define IMX_BATCH_PROLOGUE(ArgsT)                                     \
     const int bi_ = batch_index(B);                                   \
-    const ArgsT a = args[bi_];                                        \
+    const ArgsT& a = args[bi_];                                       \
     const int64_t lb = (int64_t)blockIdx.x - B.wg0[bi_];              \
     const int64_t lg = (int64_t)B.wg0[bi_ + 1] - B.wg0[bi_];          \
     (void)lb;                                                         \
@@ -355,24 +476,37 @@ hipError_t launch_sim_values(uint64_t seed, int J, uint32_t* X, hipStream_t st)
 // a3: Fill-Sketches (Alg. 1).  One thread per 4 registers.  On a rebuild,
 // covered registers (0) stay 0.
 
+
+
 __global__ __launch_bounds__(256) void k_fill(const FillArgs* __restrict__ args, Batch B)
 {
     IMX_BATCH_PROLOGUE(FillArgs);
-    const int64_t words_per_row = a.J / 4;
-    const int64_t total = a.n * words_per_row;
-    uint32_t* M32 = reinterpret_cast<uint32_t*>(a.M);
-    for (int64_t d = lb * blockDim.x + threadIdx.x; d < total; d += lg * blockDim.x) {
-        const uint32_t u = (uint32_t)(d / words_per_row);
-        const uint32_t j0 = (uint32_t)(d - (int64_t)u * words_per_row) * 4u;
-        const uint32_t pre = rank_prefix(a.seed, u);
-        const uint32_t old = a.first ? 0xffffffffu : M32[d];
-        uint32_t out = 0;
+    const int L = row_lanes(a.J);
+    const int lane = lane_id();
+    const int sub = lane % L;
+    const int chunks = a.J / 16;  // per row
+    const int64_t rows_per_iter = (int64_t)lg * (blockDim.x / L);
+    uint4* M4 = reinterpret_cast<uint4*>(a.M);
+    for (int64_t u = lb * (blockDim.x / L) + threadIdx.x / L; u < a.n; u += rows_per_iter) {
+        const uint32_t pre = rank_prefix(a.seed, (uint32_t)u);
+        uint4* row = M4 + (size_t)u * (size_t)chunks;
+        for (int c = sub; c < chunks; c += L) {
+            const uint4 old = a.first ? make_uint4(~0u, ~0u, ~0u, ~0u) : row[c];
+            const uint32_t ow[4] = {old.x, old.y, old.z, old.w};
+            uint32_t out[4];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const uint32_t r = ((old >> (8 * b)) & 0xffu) ? rank_of(pre, j0 + b) : 0u;
-            out |= r << (8 * b);
+            for (int w = 0; w < 4; ++w) {
+                uint32_t o = 0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const uint32_t j = (uint32_t)(16 * c + 4 * w + b);
+                    const uint32_t r = ((ow[w] >> (8 * b)) & 0xffu) ? rank_of(pre, j) : 0u;
+                    o |= r << (8 * b);
+                }
+                out[w] = o;
+            }
+            row[c] = make_uint4(out[0], out[1], out[2], out[3]);
         }
-        M32[d] = out;
     }
 }
 
@@ -475,8 +609,13 @@ __device__ __forceinline__ void lds_merge_word(uint32_t* w, uint32_t* dirty, int
     }
 }
 
+// Items (arc, word) each lane of a group gathers per round of the sparse merge.
+constexpr int kItemsPerLane = 2;
+
+// Six waves per SIMD: the kernel is bound by the latency of dependent
+// gathers, and this is the most waves that fit without register spills.
 template <int GS, int DPLG, bool STATS>
-__global__ __launch_bounds__(kWG) void k_propagate(const PropArgs* __restrict__ args, Batch B)
+__global__ __launch_bounds__(kWG, 6) void k_propagate(const PropArgs* __restrict__ args, Batch B)
 {
     IMX_BATCH_PROLOGUE(PropArgs);
     constexpr int NG = 64 / GS;
@@ -506,42 +645,75 @@ __global__ __launch_bounds__(kWG) void k_propagate(const PropArgs* __restrict__ 
     unsigned long long c_tasks = 0, c_rows = 0, c_wbytes = 0, c_scanned = 0, c_active = 0, c_sectors = 0;
     unsigned long long c_changed = 0;
 
-    for (int i = threadIdx.x; i < J + kBuckets + 1; i += kWG) sX[i] = a.X[i];
-    __syncthreads();
-
     const GraphDev& g = a.g;
-    const uint32_t* M32 = reinterpret_cast<const uint32_t*>(a.M);
-    uint32_t* MW = reinterpret_cast<uint32_t*>(a.M);
     // every task after a fill or after a sweep that changed many rows; else the active list
-    const bool all = a.tasks == nullptr || *a.dense != 0u;
+    const bool sweep0 = a.tasks == nullptr;  // right after a fill every head counts as changed
+    const bool all = sweep0 || *a.dense != 0u;
     const int32_t* tasks = all ? nullptr : a.tasks;
     const int64_t count = all ? g.ntasks : (int64_t)*a.task_count;
     const int64_t ngroups = lg * kWaves * NG;
+    if (*a.conv != ~0u) return;             // the build has converged
+    if (lb * kWaves * NG >= count) return;  // no task for this workgroup (uniform)
 
-    for (int64_t qb = (lb * kWaves + wave) * NG; qb < count; qb += ngroups) {
-        const int64_t q = qb + gi;
-        const bool valid = q < count;
+    for (int i = threadIdx.x; i < J + kBuckets + 1; i += kWG) sX[i] = a.X[i];
+    __syncthreads();
+
+    const uint32_t* M32 = reinterpret_cast<const uint32_t*>(a.M);
+    uint32_t* MW = reinterpret_cast<uint32_t*>(a.M);
+    const uint32_t* chg_prev = a.chg_prev;
+
+    // The id of the group's next task is loaded one iteration ahead.
+    int64_t qb = (lb * kWaves + wave) * NG;
+    int32_t t_next = -1;
+    if (qb + gi < count) t_next = tasks ? tasks[qb + gi] : (int32_t)(qb + gi);
+
+    for (; qb < count; qb += ngroups) {
+        const int32_t t = t_next;
+        const bool valid = t >= 0;
         int32_t u = 0;
         int64_t e0 = 0, e1 = 0;
         bool split = false;
         if (valid) {
-            const int32_t t = tasks ? tasks[q] : (int32_t)q;
             u = g.task_u[t];
             e0 = g.task_e0[t];
             const uint32_t len = g.task_len[t];
             e1 = e0 + (int64_t)(len & 0x7fffffffu);
             split = (len >> 31) != 0u;
         }
+        {
+            const int64_t qn = qb + ngroups + gi;
+            t_next = -1;
+            if (qn < count) t_next = tasks ? tasks[qn] : (int32_t)qn;
+        }
         if (STATS && valid && lig == 0) ++c_tasks;
         const int nch = valid ? (int)((e1 - e0 + GS - 1) / GS) : 0;
         const int maxch = wave_max_i32(nch);
-        // stage u's row in LDS and clear the dirty bitmap
+
+        // Independent loads issued together: u's row, the first chunk of
+        // arcs, and u's in-task range (used only if the row changes).
+        uint32_t rw[DPLG];
+        const uint32_t* Mu = M32 + (size_t)u * (size_t)Jw;
+#pragma unroll
+        for (int i = 0; i < DPLG; ++i) {
+            const int idx = lig + GS * i;
+            rw[i] = (valid && idx < Jw) ? Mu[idx] : 0u;
+        }
+        int32_t v_nx = 0;
+        uint32_t w_nx = 0;
+        if (e0 + lig < e1) {
+            v_nx = g.col[e0 + lig];
+            w_nx = g.W[e0 + lig];
+        }
+        int32_t in_first = 0, in_cnt = 0;
+        if (valid && lig == 0) {
+            in_first = g.in_task_start[u];
+            in_cnt = g.in_task_start[u + 1] - in_first;
+        }
         if (valid) {
-            const uint32_t* Mu = M32 + (size_t)u * (size_t)Jw;
 #pragma unroll
             for (int i = 0; i < DPLG; ++i) {
                 const int idx = lig + GS * i;
-                if (idx < Jw) rowW[idx] = Mu[idx];
+                if (idx < Jw) rowW[idx] = rw[i];
             }
             if (lig < 32) dirty[lig] = 0u;
             if (GS == 16) dirty[lig + 16] = 0u;
@@ -550,13 +722,21 @@ __global__ __launch_bounds__(kWG) void k_propagate(const PropArgs* __restrict__ 
         for (int c = 0; c < maxch; ++c) {
             const int64_t e = e0 + (int64_t)c * GS + lig;
             int cnt = 0, lo = 0, hi = 0;
-            int32_t v = 0;
-            uint32_t h = 0, w = 0;
+            const int32_t v = v_nx;
+            const uint32_t w = w_nx;
+            uint32_t h = 0;
+            if (c + 1 < maxch) {  // next chunk's arcs
+                const int64_t en = e + GS;
+                v_nx = 0;
+                w_nx = 0;
+                if (en < e1) {
+                    v_nx = g.col[en];
+                    w_nx = g.W[en];
+                }
+            }
             bool act_arc = false;
             if (e < e1) {
-                v = g.col[e];
-                w = g.W[e];
-                act_arc = (a.chg_prev[(uint32_t)v >> 5] >> (v & 31)) & 1u;
+                act_arc = sweep0 || ((chg_prev[(uint32_t)v >> 5] >> (v & 31)) & 1u);
                 if (act_arc && w != 0u) {
                     h = arc_hash((uint32_t)u, (uint32_t)v);
                     candidate_range(sX, sT, J, h, w, lo, hi);
@@ -576,24 +756,43 @@ __global__ __launch_bounds__(kWG) void k_propagate(const PropArgs* __restrict__ 
             const int nd = (cnt > 0 && !dense) ? (((hi - 1) >> 2) - (lo >> 2) + 1) : 0;
             wave_lds_sync();
 
-            // dense arcs: the group merges v's row word by word, no collisions
+            // dense arcs: the group merges v's row word by word (each lane owns
+            // fixed words, so no collisions); DB arcs' loads are in flight at once
+            // (one measured best: more raise register pressure past the occupancy target)
+            constexpr int DB = 1;
             unsigned long long rem = (__ballot(dense) & gmask) >> gbase;
             const int maxd = wave_max_i32(__popcll(rem));
-            for (int k = 0; k < maxd; ++k) {
-                const bool has = rem != 0ull;
-                const int ak = has ? __ffsll((long long)rem) - 1 : 0;
-                rem &= rem - 1ull;
-                const int vk = __shfl(v, gbase + ak, 64);
-                const uint32_t hk = __shfl(h, gbase + ak, 64), wk = __shfl(w, gbase + ak, 64);
-                const int lok = __shfl(lo, gbase + ak, 64), hik = __shfl(hi, gbase + ak, 64);
-                if (has) {
-                    const uint32_t* src = M32 + (size_t)vk * (size_t)Jw;
+            for (int k = 0; k < maxd; k += DB) {
+                bool has[DB];
+                int vk[DB], lok[DB], hik[DB];
+                uint32_t hk[DB], wk[DB];
+                uint32_t sv[DB][DPLG];
+#pragma unroll
+                for (int x = 0; x < DB; ++x) {
+                    has[x] = rem != 0ull;
+                    const int ak = has[x] ? __ffsll((long long)rem) - 1 : 0;
+                    rem &= rem - 1ull;
+                    vk[x] = __shfl(v, gbase + ak, 64);
+                    hk[x] = __shfl(h, gbase + ak, 64);
+                    wk[x] = __shfl(w, gbase + ak, 64);
+                    lok[x] = __shfl(lo, gbase + ak, 64);
+                    hik[x] = __shfl(hi, gbase + ak, 64);
+                    const uint32_t* src = M32 + (size_t)vk[x] * (size_t)Jw;
 #pragma unroll
                     for (int i = 0; i < DPLG; ++i) {
                         const int idx = lig + GS * i;
-                        if (idx < Jw && 4 * idx + 3 >= lok && 4 * idx < hik) {
+                        sv[x][i] = (has[x] && idx < Jw && 4 * idx + 3 >= lok[x] && 4 * idx < hik[x]) ? src[idx] : 0u;
+                    }
+                }
+#pragma unroll
+                for (int x = 0; x < DB; ++x) {
+                    if (!has[x]) continue;
+#pragma unroll
+                    for (int i = 0; i < DPLG; ++i) {
+                        const int idx = lig + GS * i;
+                        if (idx < Jw && 4 * idx + 3 >= lok[x] && 4 * idx < hik[x]) {
                             const uint32_t val =
-                                src[idx] & live_mask4(*reinterpret_cast<const uint4*>(&sX[4 * idx]), hk, wk);
+                                sv[x][i] & live_mask4(*reinterpret_cast<const uint4*>(&sX[4 * idx]), hk[x], wk[x]);
                             const uint32_t cur = rowW[idx];
                             const uint32_t want = bytemax4(cur, val);
                             if (want != cur) {
@@ -602,7 +801,8 @@ __global__ __launch_bounds__(kWG) void k_propagate(const PropArgs* __restrict__ 
                             }
                         }
                     }
-                    if (STATS && lig == 0) c_sectors += (unsigned long long)(((hik - 1) >> 6) - (lok >> 6) + 1);
+                    if (STATS && lig == 0)
+                        c_sectors += (unsigned long long)(((hik[x] - 1) >> 6) - (lok[x] >> 6) + 1);
                 }
             }
 
@@ -618,32 +818,26 @@ __global__ __launch_bounds__(kWG) void k_propagate(const PropArgs* __restrict__ 
             est[lig] = incl - nd;
             if (STATS) esec[lig] = 0ull;
             wave_lds_sync();
-            for (int r = 0; r < maxtot; r += 2 * GS) {
-                uint32_t val0 = 0u, val1 = 0u, m0 = 0u, m1 = 0u;
-                int d0 = 0, d1 = 0;
-                const int i0 = r + lig, i1 = r + GS + lig;
-                if (i0 < total) {
-                    const int k = group_owner<GS>(est, i0);
-                    d0 = edl[k] + (i0 - est[k]);
-                    m0 = live_mask4(*reinterpret_cast<const uint4*>(&sX[4 * d0]), eh[k], eW[k]);
-                    if (m0) {
-                        val0 = M32[(size_t)ev[k] * (size_t)Jw + (size_t)d0];
-                        if (STATS) atomicOr(&esec[k], 1ull << ((4 * d0) >> 6));
+            for (int r = 0; r < maxtot; r += kItemsPerLane * GS) {
+                uint32_t val[kItemsPerLane];
+                int dw[kItemsPerLane];
+#pragma unroll
+                for (int x = 0; x < kItemsPerLane; ++x) {
+                    const int ii = r + x * GS + lig;
+                    val[x] = 0u;
+                    dw[x] = 0;
+                    if (ii < total) {
+                        const int k = group_owner<GS>(est, ii);
+                        dw[x] = edl[k] + (ii - est[k]);
+                        const uint32_t m = live_mask4(*reinterpret_cast<const uint4*>(&sX[4 * dw[x]]), eh[k], eW[k]);
+                        if (m) {
+                            val[x] = M32[(size_t)ev[k] * (size_t)Jw + (size_t)dw[x]] & m;
+                            if (STATS) atomicOr(&esec[k], 1ull << ((4 * dw[x]) >> 6));
+                        }
                     }
                 }
-                if (i1 < total) {
-                    const int k = group_owner<GS>(est, i1);
-                    d1 = edl[k] + (i1 - est[k]);
-                    m1 = live_mask4(*reinterpret_cast<const uint4*>(&sX[4 * d1]), eh[k], eW[k]);
-                    if (m1) {
-                        val1 = M32[(size_t)ev[k] * (size_t)Jw + (size_t)d1];
-                        if (STATS) atomicOr(&esec[k], 1ull << ((4 * d1) >> 6));
-                    }
-                }
-                val0 &= m0;
-                val1 &= m1;
-                lds_merge_word(&rowW[d0], dirty, d0, val0, val0 != 0u);
-                lds_merge_word(&rowW[d1], dirty, d1, val1, val1 != 0u);
+#pragma unroll
+                for (int x = 0; x < kItemsPerLane; ++x) lds_merge_word(&rowW[dw[x]], dirty, dw[x], val[x], val[x] != 0u);
             }
             if (STATS) {
                 c_sectors += (unsigned long long)__popcll(esec[lig]);
@@ -655,22 +849,22 @@ __global__ __launch_bounds__(kWG) void k_propagate(const PropArgs* __restrict__ 
         // store changed words of u's row
         bool changed = false;
         if (touched) {
-            uint32_t* Mu = MW + (size_t)u * (size_t)Jw;
+            uint32_t* Mw = MW + (size_t)u * (size_t)Jw;
 #pragma unroll
             for (int i = 0; i < DPLG; ++i) {
                 const int idx = lig + GS * i;
                 if (idx < Jw && ((dirty[idx >> 5] >> (idx & 31)) & 1u)) {
                     const uint32_t nwd = rowW[idx];
                     if (!split) {
-                        Mu[idx] = nwd;
+                        Mw[idx] = nwd;
                         changed = true;
                         if (STATS) c_wbytes += 4;
                     } else {
-                        uint32_t cur = Mu[idx];
+                        uint32_t cur = Mw[idx];
                         for (;;) {
                             const uint32_t want = bytemax4(cur, nwd);
                             if (want == cur) break;
-                            const uint32_t prev = atomicCAS(&Mu[idx], cur, want);
+                            const uint32_t prev = atomicCAS(&Mw[idx], cur, want);
                             if (prev == cur) {
                                 changed = true;
                                 if (STATS) c_wbytes += 4;
@@ -683,21 +877,23 @@ __global__ __launch_bounds__(kWG) void k_propagate(const PropArgs* __restrict__ 
             }
         }
         const bool gchanged = (__ballot(changed) & gmask) != 0ull;
-        // flag u once per sweep; the first flagger activates u's pullers
+        // Flag u once per sweep; the first flagger queues u's in-tasks.  A
+        // row with one task has one flagger, so its flag needs no reply.
         bool first = false;
         if (gchanged && lig == 0) {
             const uint32_t bit = 1u << (u & 31);
-            first = !(atomicOr(&a.chg_next[(uint32_t)u >> 5], bit) & bit);
+            if (!split) {
+                atomicOr(&a.chg_next[(uint32_t)u >> 5], bit);
+                first = true;
+            } else {
+                first = !(atomicOr(&a.chg_next[(uint32_t)u >> 5], bit) & bit);
+            }
         }
-        first = __shfl(first ? 1 : 0, gbase, 64) != 0;
-        int n_in = 0, i_first = 0;
-        if (first && lig == 0) {
-            ++c_changed;
-            i_first = g.in_task_start[u];
-            n_in = g.in_task_start[u + 1] - i_first;
-        }
-        wl_append_ranges(chl, n_in, i_first);
+        if (first) ++c_changed;
+        wl_append_ranges(chl, first ? in_cnt : 0, in_first);
     }
+    // per-wave flushes here: measured faster than a workgroup-wide flush,
+    // whose barrier holds finished waves until the slowest one of the group
     wl_flush(chl);
     {
         const unsigned long long tot = wave_sum_u64(c_changed);
@@ -819,19 +1015,22 @@ hipError_t launch_propagate(const PropArgs* args, const Batch& B, int maxJ, int 
     });
 }
 
-// Before sweep s: clear the bitmap sweep s writes, the activation bitmap and
-// the counters sweep s and its mark step accumulate into.  Sweep 0 (right
-// after a fill) also marks every row as changed.
-__global__ __launch_bounds__(256) void k_sweep_prep(const PrepArgs* __restrict__ args, Batch B)
+// Before sweep s: clear the bitmap sweep s writes and the counters sweep s
+// accumulates into, and compact the vertices the mark step of sweep s-1
+// flagged into sweep s's active task list (unless sweep s visits every task).
+// Sweep 0 (right after a fill) marks every row as changed.
+__global__ __launch_bounds__(kWG) void k_sweep_prep(const PrepArgs* __restrict__ args, Batch B)
 {
     IMX_BATCH_PROLOGUE(PrepArgs);
+    __shared__ int32_t wbuf[kWaves][kWaveBufCap];
     const SweepDev& s = a.s;
     const int sweep = a.sweep;
     const int64_t i0 = lb * blockDim.x + threadIdx.x;
+    if (sweep > 0 && *s.conv != ~0u) return;  // the build has converged
+    if (sweep == 0 && i0 == 0) *s.conv = ~0u;   // a new build starts
     uint32_t* nxt = s.chg[(sweep + 1) & 1];
     for (int64_t i = i0; i < a.nwords; i += lg * blockDim.x) {
         nxt[i] = 0u;
-        s.act_bm[i] = 0u;
         if (sweep == 0) s.chg[0][i] = 0xffffffffu;
     }
     if (i0 == 0) {
@@ -839,32 +1038,43 @@ __global__ __launch_bounds__(256) void k_sweep_prep(const PrepArgs* __restrict__
         s.chg_count[sweep & 3] = 0u;
         s.act_count[(sweep + 1) & 3] = 0u;
     }
+    if (sweep > 0 && s.dense[sweep & 3] == 0u && s.chg_count[(sweep - 1) & 3] != 0u) {
+        __shared__ uint32_t s_flush[kWaves + 1];
+        const int wave = (int)(threadIdx.x >> 6);
+        WaveList L{wbuf[wave], 0, s.act_tasks[sweep & 1], &s.act_count[sweep & 3]};
+        compact_flags<false>(s.act8, a.n, a.task_start, L, L, nullptr, 0u, lb * kWaves + wave, lg * kWaves);
+        wg_flush(L, s_flush);
+    }
 }
 
 hipError_t launch_sweep_prep(const PrepArgs* args, const Batch& B, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_sweep_prep, dim3(B.wg0[B.nq]), dim3(256), 0, st, args, B);
+    hipLaunchKernelGGL(k_sweep_prep, dim3(B.wg0[B.nq]), dim3(kWG), 0, st, args, B);
     return hipGetLastError();
 }
 
-// Mark step of sweep s: every source w of an in-arc of a changed row becomes
-// active for sweep s+1 (once, through the activation bitmap) and its
-// out-tasks are appended to the next active task list.
+// Mark step of sweep s: every source w of an in-arc of a changed row is
+// flagged active for sweep s+1 (plain byte stores; the prep step of sweep s+1
+// compacts the flags into the task list).
 __global__ __launch_bounds__(kWG) void k_mark(const MarkArgs* __restrict__ args, Batch B)
 {
     IMX_BATCH_PROLOGUE(MarkArgs);
     const GraphDev& g = a.g;
     const SweepDev& s = a.s;
     const int sweep = a.sweep;
-    __shared__ int32_t wbuf[kWaves][kWaveBufCap];
     const int lane = lane_id();
     // Many changed rows (more than n / dense_div): the next sweep visits every
     // task (with per-arc changed-head tests) instead of building a list.
-    const bool dense = s.rows_changed[sweep & 3] * (unsigned long long)a.dense_div > (unsigned long long)g.n;
+    if (*s.conv != ~0u) return;  // converged before this sweep
+    const unsigned long long changed = s.rows_changed[sweep & 3];
+    if (changed == 0ull) {       // sweep s changed nothing: the build has converged at s
+        if (lb == 0 && threadIdx.x == 0) *s.conv = (uint32_t)sweep;
+        return;
+    }
+    const bool dense = changed * (unsigned long long)a.dense_div > (unsigned long long)g.n;
     if (lb == 0 && threadIdx.x == 0) s.dense[(sweep + 1) & 3] = dense ? 1u : 0u;
     if (dense) return;
     const uint32_t count = s.chg_count[sweep & 3];
-    WaveList nxt{wbuf[threadIdx.x >> 6], 0, s.act_tasks[(sweep + 1) & 1], &s.act_count[(sweep + 1) & 3]};
     const int64_t nw = lg * kWaves;
     for (int64_t q = lb * kWaves + (threadIdx.x >> 6); q < (int64_t)count; q += nw) {
         const int32_t it = s.chg_list[q];
@@ -872,22 +1082,8 @@ __global__ __launch_bounds__(kWG) void k_mark(const MarkArgs* __restrict__ args,
         const int64_t e0 = g.in_task_e0[it];
         const int64_t ve = g.in_rowptr[v + 1];
         const int64_t e1 = (e0 + g.in_split < ve) ? e0 + g.in_split : ve;
-        for (int64_t cb = e0; cb < e1; cb += 64) {
-            const int64_t e = cb + lane;
-            int c = 0;
-            int32_t first = 0;
-            if (e < e1) {
-                const int32_t w = g.in_col[e];
-                const uint32_t bit = 1u << (w & 31);
-                if (!(atomicOr(&s.act_bm[(uint32_t)w >> 5], bit) & bit)) {
-                    first = g.task_start[w];
-                    c = g.task_start[w + 1] - first;
-                }
-            }
-            wl_append_ranges(nxt, c, first);
-        }
+        for (int64_t e = e0 + lane; e < e1; e += 64) s.act8[g.in_col[e]] = 1u;
     }
-    wl_flush(nxt);
 }
 
 hipError_t launch_mark(const MarkArgs* args, const Batch& B, hipStream_t st)
@@ -900,30 +1096,59 @@ hipError_t launch_mark(const MarkArgs* args, const Batch& B, hipStream_t st)
 // a5: estimate terms per vertex (Eq. 7 harmonic form over uncovered registers):
 // Ju = #registers != 0, Hu = sum of 2^(33 - M).  One wave per row.
 
+// Sum of x over the aligned group of L lanes (L a power of two).
+__device__ __forceinline__ uint32_t group_sum_u32(uint32_t x, int L)
+{
+    for (int d = L >> 1; d > 0; d >>= 1) x += __shfl_xor(x, d, 64);
+    return x;
+}
+__device__ __forceinline__ unsigned long long group_sum_u64(unsigned long long x, int L)
+{
+    for (int d = L >> 1; d > 0; d >>= 1) x += __shfl_xor(x, d, 64);
+    return x;
+}
+
+// Ju and Hu terms of one 32-bit word of registers (covered registers are 0).
+__device__ __forceinline__ void est_word(uint32_t d, uint32_t& c, unsigned long long& h)
+{
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const uint32_t r = (d >> (8 * b)) & 0xffu;
+        if (r) {
+            ++c;
+            h += 1ull << (33u - r);
+        }
+    }
+}
+
 __global__ __launch_bounds__(kWG) void k_estimate(const EstArgs* __restrict__ args, Batch B)
 {
     IMX_BATCH_PROLOGUE(EstArgs);
+    const int L = row_lanes(a.J);
     const int lane = lane_id();
-    const int Jw = a.J >> 2;
+    const int sub = lane % L;
+    const int chunks = a.J / 16;
+    const int64_t rows_per_wave_iter = 64 / L;
     const int64_t nw = lg * kWaves;
-    for (int64_t v = lb * kWaves + (threadIdx.x >> 6); v < a.n; v += nw) {
-        const uint32_t* row = reinterpret_cast<const uint32_t*>(a.M + (size_t)v * (size_t)a.J);
+    const uint4* M4 = reinterpret_cast<const uint4*>(a.M);
+    // every lane of a wave runs the same number of iterations (uniform shuffles)
+    for (int64_t vb = (lb * kWaves + (threadIdx.x >> 6)) * rows_per_wave_iter; vb < a.n; vb += nw * rows_per_wave_iter) {
+        const int64_t v = vb + lane / L;
         uint32_t c = 0;
         unsigned long long h = 0;
-        for (int idx = lane; idx < Jw; idx += 64) {
-            const uint32_t d = row[idx];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const uint32_t r = (d >> (8 * b)) & 0xffu;
-                if (r) {
-                    ++c;
-                    h += 1ull << (33u - r);
-                }
+        if (v < a.n) {
+            const uint4* row = M4 + (size_t)v * (size_t)chunks;
+            for (int k = sub; k < chunks; k += L) {
+                const uint4 q = row[k];
+                est_word(q.x, c, h);
+                est_word(q.y, c, h);
+                est_word(q.z, c, h);
+                est_word(q.w, c, h);
             }
         }
-        c = wave_sum_u32(c);
-        h = wave_sum_u64(h);
-        if (lane == 0) {
+        c = group_sum_u32(c, L);
+        h = group_sum_u64(h, L);
+        if (sub == 0 && v < a.n) {
             a.Ju[v] = c;
             a.Hu[v] = h;
         }
@@ -1046,6 +1271,7 @@ __global__ __launch_bounds__(64) void k_cascade_seed(const SeedArgs* __restrict_
             a.seeds[a.k] = -1;
             c.qsize[0] = c.qsize[1] = c.qsize[2] = c.qsize[3] = 0;
             *c.ntouched = 0;
+            *c.level_end = ~0u;
         }
         return;
     }
@@ -1072,7 +1298,7 @@ __global__ __launch_bounds__(64) void k_cascade_seed(const SeedArgs* __restrict_
         c.qsize[2] = 0;
         c.qsize[3] = 0;
         c.qsize[1] = (uint32_t)nt;
-        c.stamp[s] = a.level_id1;
+        *c.level_end = ~0u;
         c.touched[0] = s;
         *c.ntouched = 1;
         c.touch_stamp[s] = a.cascade_id;
@@ -1091,10 +1317,10 @@ hipError_t launch_cascade_seed(const SeedArgs* args, const Batch& B, hipStream_t
 // that contain the marker (ED, ascending); each arc's candidate range selects
 // a contiguous slice of ED, and the (arc, word) items are dealt to lanes.
 // Heads still uncovered where the arc is live get the level-t marker (byte
-// stores) and their out-tasks join Q_{t+1} (once per level, via stamp).
+// stores) and are flagged in lv8; the compaction after the level turns the
+// flags into Q_{t+1}.
 
-
-constexpr int kLevelBufWords = 6 * 64 + 2 * kWaveBufCap;
+constexpr int kLevelBufWords = 5 * 64;
 
 __device__ __forceinline__ int lower_bound_i32(const int* A, int n, int key)
 {
@@ -1119,6 +1345,14 @@ __global__ __launch_bounds__(kWG) void k_cascade_level(const LevelArgs* __restri
     const int Jw = J >> 2;
     const int wave = (int)(threadIdx.x >> 6);
     const int lane = lane_id();
+
+    const uint32_t qn = a.c.qsize[a.t & 3];
+    if (lb == 0 && threadIdx.x == 0) {
+        a.c.qsize[(a.t + 1) & 3] = 0;  // Q_{t+1}, filled by the compaction
+        if (qn == 0u && *a.c.level_end == ~0u) *a.c.level_end = (uint32_t)a.t;
+    }
+    if (lb * kWaves >= (int64_t)qn) return;  // no task for this workgroup (uniform)
+
     uint32_t* sX = smem;
     const uint32_t* sT = smem + J;
     const int XT = J + kTableWords;
@@ -1129,19 +1363,12 @@ __global__ __launch_bounds__(kWG) void k_cascade_level(const LevelArgs* __restri
     uint32_t* eW = eh + 64;
     int* epl = reinterpret_cast<int*>(eW + 64);
     int* est = epl + 64;
-    uint32_t* efl = reinterpret_cast<uint32_t*>(est + 64);
-    int32_t* qbuf = reinterpret_cast<int32_t*>(efl + 64);
 
-    if (lb == 0 && threadIdx.x == 0) a.c.qsize[(a.t + 2) & 3] = 0;
     for (int i = threadIdx.x; i < J + kBuckets + 1; i += kWG) sX[i] = a.X[i];
     __syncthreads();
 
-    const uint32_t qn = a.c.qsize[a.t & 3];
     const int32_t* Q = a.c.q[a.t & 1];
-    int32_t* Qn = a.c.q[(a.t + 1) & 1];
-    uint32_t* qn_ctr = &a.c.qsize[(a.t + 1) & 3];
-    WaveList qlist{qbuf, 0, Qn, qn_ctr};
-    WaveList tlist{qbuf + kWaveBufCap, 0, a.c.touched, a.c.ntouched};
+    uint8_t* lv8 = a.c.lv8;
     const uint32_t mk_prev = marker(a.t - 1);
     const uint32_t mk_cur = marker(a.t);
     const GraphDev& g = a.g;
@@ -1152,8 +1379,7 @@ __global__ __launch_bounds__(kWG) void k_cascade_level(const LevelArgs* __restri
         const int32_t t = Q[i];
         const int32_t u = g.task_u[t];
         const int64_t e0 = g.task_e0[t];
-        const int64_t re = g.rowptr[u + 1];
-        const int64_t e1 = (e0 + g.split < re) ? e0 + g.split : re;
+        const int64_t e1 = e0 + (int64_t)(g.task_len[t] & 0x7fffffffu);
         const uint32_t* Mu = M32 + (size_t)u * (size_t)Jw;
         int nE = 0;
         for (int base = 0; base < Jw; base += 64) {
@@ -1194,7 +1420,6 @@ __global__ __launch_bounds__(kWG) void k_cascade_level(const LevelArgs* __restri
             eW[lane] = w;
             epl[lane] = pl;
             est[lane] = incl - cnt;
-            efl[lane] = 0u;
             wave_lds_sync();
             for (int r = 0; r < total; r += 64) {
                 const int idx = r + lane;
@@ -1204,36 +1429,22 @@ __global__ __launch_bounds__(kWG) void k_cascade_level(const LevelArgs* __restri
                     uint32_t m = eq_mask4(roww[d], mk_prev) &
                                  live_mask4(*reinterpret_cast<const uint4*>(&sX[4 * d]), eh[k], eW[k]);
                     if (m) {
-                        const size_t off = (size_t)ev[k] * (size_t)Jw + (size_t)d;
+                        const int32_t vk = ev[k];
+                        const size_t off = (size_t)vk * (size_t)Jw + (size_t)d;
                         m &= uncovered_mask4(M32[off]);
                         if (m) {
                             uint8_t* p = a.M + off * 4;
 #pragma unroll
                             for (int b = 0; b < 4; ++b)
                                 if ((m >> (8 * b)) & 1u) p[b] = (uint8_t)mk_cur;
-                            efl[k] = 1u;
+                            lv8[vk] = 1u;
                         }
                     }
                 }
             }
             wave_lds_sync();
-            bool push_t = false;
-            int c = 0;
-            int32_t first = 0;
-            if (efl[lane]) {
-                if (atomicMax(&a.c.stamp[v], a.level_id) < a.level_id) {
-                    first = g.task_start[v];
-                    c = g.task_start[v + 1] - first;
-                }
-                push_t = atomicMax(&a.c.touch_stamp[v], a.cascade_id) < a.cascade_id;
-            }
-            wl_append_ranges(qlist, c, first);
-            wl_append_ranges(tlist, push_t ? 1 : 0, v);
-            wave_lds_sync();
         }
     }
-    wl_flush(qlist);
-    wl_flush(tlist);
 }
 
 static size_t level_lds(int J)
@@ -1271,12 +1482,36 @@ hipError_t launch_cascade_level(const LevelArgs* args, const Batch& B, int maxJ,
     return hipGetLastError();
 }
 
+// After level t: the flagged vertices become frontier Q_{t+1} (their
+// out-tasks) and join the touched list once per cascade.
+__global__ __launch_bounds__(kWG) void k_cascade_compact(const LevelCompactArgs* __restrict__ args, Batch B)
+{
+    IMX_BATCH_PROLOGUE(LevelCompactArgs);
+    __shared__ int32_t wbuf[kWaves][2 * kWaveBufCap];
+    const CascadeDev& c = a.c;
+    if (c.qsize[a.t & 3] == 0u) return;  // empty level: nothing was flagged
+    const int wave = (int)(threadIdx.x >> 6);
+    WaveList L{wbuf[wave], 0, c.q[(a.t + 1) & 1], &c.qsize[(a.t + 1) & 3]};
+    WaveList T{wbuf[wave] + kWaveBufCap, 0, c.touched, c.ntouched};
+    __shared__ uint32_t s_flush[kWaves + 1];
+    compact_flags<true>(c.lv8, a.n, a.task_start, L, T, c.touch_stamp, a.cascade_id, lb * kWaves + wave, lg * kWaves);
+    wg_flush(L, s_flush);
+    wg_flush(T, s_flush);
+}
+
+hipError_t launch_cascade_compact(const LevelCompactArgs* args, const Batch& B, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cascade_compact, dim3(B.wg0[B.nq]), dim3(kWG), 0, st, args, B);
+    return hipGetLastError();
+}
+
 // End of a cascade: markers become 0 in every touched row; Ju/Hu of touched
 // rows are recomputed and T grows by the number of newly covered registers.
 __global__ __launch_bounds__(kWG) void k_cascade_finalize(const FinArgs* __restrict__ args, Batch B)
 {
     IMX_BATCH_PROLOGUE(FinArgs);
     const CascadeDev& c = a.c;
+    if (*c.level_end == ~0u) return;  // the cascade is still running
     const int lane = lane_id();
     const int Jw = a.J >> 2;
     const uint32_t nt = *c.ntouched;
@@ -1311,7 +1546,8 @@ __global__ __launch_bounds__(kWG) void k_cascade_finalize(const FinArgs* __restr
             dT += (unsigned long long)(old - cnt);
         }
     }
-    if (lane == 0 && dT) atomicAdd(c.T, dT);
+    __shared__ unsigned long long s_sum[kWaves];
+    wg_add_u64(dT, c.T, s_sum);
 }
 
 hipError_t launch_cascade_finalize(const FinArgs* args, const Batch& B, hipStream_t st)
