@@ -252,7 +252,8 @@ def served_main(args):
         trace = [(float(t), *r) for t, r in zip(arr, reqs)]
         row = {"load": load, "lambda_qps": lam}
         for mode, mq in (("continuous_batching", args.served_slots), ("serial", 1)):
-            srv = serve.Server(graphs, max_queries=mq, stream=stream).start()
+            lanes = [int(x) << 20 for x in args.served_lanes_mib.split(",")] if mode != "serial" else None
+            srv = serve.Server(graphs, max_queries=mq, stream=stream, lanes=lanes).start()
             res, span = serve.replay(srv, trace)
             srv.stop()
             row[mode] = serve.latency_summary(res, span)
@@ -265,7 +266,8 @@ def served_main(args):
         out["levels"].append(row)
     out["value"] = max(r["continuous_batching"]["throughput_qps"] for r in out["levels"])
     out["config"] = {"workload": "served_rmat" + "-".join(map(str, scales)) + "_p0.01+wc_J128|512_K10-100",
-                     "queries_per_level": nq, "slots": args.served_slots}
+                     "queries_per_level": nq, "slots_per_lane": args.served_slots,
+                     "lanes_mib": args.served_lanes_mib}
     print(json.dumps(out), flush=True)
 
 
@@ -284,7 +286,9 @@ def main():
     ap.add_argument("--served-scales", default="16,17,18,19,20,21,22,22")
     ap.add_argument("--served-queries", type=int, default=64)
     ap.add_argument("--served-loads", default="0.5,0.8,1.0")
-    ap.add_argument("--served-slots", type=int, default=16)
+    ap.add_argument("--served-slots", type=int, default=16, help="queries per lane at once")
+    ap.add_argument("--served-lanes-mib", default="128,1024",
+                    help="footprint bounds (MiB) of the serving lanes; larger queries take the last lane")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="turn rocprofv3 counter_collection.csv files of this workload and of the copy "
                          "calibration into profiles/propagate_<workload>_pmc.json and print it")
@@ -388,8 +392,9 @@ def main():
                            "kernel": "k_propagate", "alg_bytes_per_launch": bpl,
                            "avg_launch_us": tpl * 1e6,
                            "per_launch": {k: st[k] / st["prop_launches"] for k in
-                                          ("prop_tasks", "prop_rows_read", "prop_bytes_written",
-                                           "prop_arcs_scanned", "prop_arcs_active", "prop_sectors")}}
+                                          ("prop_rows_visited", "prop_rows_changed", "prop_arcs_active",
+                                           "prop_sectors", "prop_tasks", "prop_rows_read", "prop_bytes_written",
+                                           "prop_arcs_scanned")}}
         print(f"[bench] roofline: {bpl / 1e6:.1f} MB/launch, {tpl * 1e6:.1f} us/launch, {achieved:.0f} GB/s",
               file=sys.stderr, flush=True)
 

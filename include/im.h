@@ -53,21 +53,28 @@ typedef struct im_stats {
     int64_t cascade_levels;  /* union-frontier levels over all cascades         */
     double build_ms;         /* im_sketch_build: fill + propagation + estimate  */
     double select_ms;        /* im_select_seeds, end to end                     */
-    double propagate_ms;     /* propagation phases (build and rebuilds), from the
-                                first sweep's start to the last sweep's end      */
-    double cascade_ms;       /* covering cascades only                          */
-    int64_t prop_launches;   /* propagation kernel launches (= total_sweeps)    */
+    double propagate_ms;     /* device time of the steps that ran this query's
+                                propagation sweeps (shared steps count fully)   */
+    double cascade_ms;       /* device time of the steps that ran this query's
+                                covering cascades (shared steps count fully)    */
+    int64_t prop_launches;   /* propagation kernel launches; a step launches a
+                                fixed number of sweeps, and those after the
+                                build converged return at once                  */
     double prop_kernel_ms;   /* sum of per-launch propagation kernel times      */
-    /* Algorithmic traffic of the propagation kernel, counted by its
+    /* Algorithmic traffic of the propagation sweeps, counted by the kernel's
      * instrumented variant when profiling level 2 is on (else all 0):
-     *   bytes = 28*tasks + 4*arcs_scanned + 4*arcs_active + 64*sectors
-     *         + J*rows_read + bytes_written + (n/4)*prop_launches
-     * (task record + row bounds; head ids; thresholds of arcs whose head
-     * changed; 64-byte sectors of head rows holding live registers; own rows
-     * read; changed register words stored; frontier bitmaps read and cleared). */
+     *   bytes = (8 + J)*rows_visited + J*rows_changed + 8*arcs_active + 64*sectors
+     * summed over sweeps, where rows_visited = rows with at least one arc whose
+     * head changed in the previous sweep (row bounds and own registers read),
+     * rows_changed = rows stored, arcs_active = such arcs (head id and
+     * threshold), sectors = 64-byte sectors of their heads' rows that hold
+     * simulations where the arc is live.  The other counters are the kernel's
+     * own events: tasks visited, rows staged with candidates, changed 32-bit
+     * words x 4 stored, arcs whose head id was read. */
     double prop_alg_bytes;
     int64_t prop_tasks, prop_rows_read, prop_bytes_written;
     int64_t prop_arcs_scanned, prop_arcs_active, prop_sectors;
+    int64_t prop_rows_visited, prop_rows_changed;
 } im_stats;
 
 /* Message of the last failed call on this thread ("" if none). */

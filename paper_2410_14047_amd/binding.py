@@ -45,6 +45,8 @@ class im_stats(ctypes.Structure):
         ("prop_arcs_scanned", ctypes.c_int64),
         ("prop_arcs_active", ctypes.c_int64),
         ("prop_sectors", ctypes.c_int64),
+        ("prop_rows_visited", ctypes.c_int64),
+        ("prop_rows_changed", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -72,6 +74,16 @@ def lib() -> ctypes.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"HIP library missing: {LIB_PATH} (run __graft_entry__.build())")
+        # One HIP runtime per process: PyTorch ships its own copy of the HIP
+        # runtime, with the same soname as the system one this library links.
+        # Loading PyTorch first makes the library bind to that copy, so the
+        # two share one runtime, device context and stream namespace (torch
+        # streams can be passed in).  Loaded the other way round, two
+        # runtimes would coexist and the second one could not open the GPU.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         P, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
         L.im_last_error.argtypes = []

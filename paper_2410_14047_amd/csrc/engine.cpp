@@ -71,6 +71,8 @@ struct Query {
     uint32_t* pickJ = nullptr;
     unsigned long long* pickH = nullptr;
     PropCounters* pc = nullptr;
+    uint32_t* vstamp = nullptr;    // instrumented runs: per-row launch stamps
+    uint32_t prop_launch_id = 0;   // instrumented runs: id of the last propagation launch
     // host state
     Stage stage = Stage::Fill;
     bool fresh = true;      // the next fill is the sketch's first: every register uncovered
@@ -99,6 +101,8 @@ public:
         if (args_host_) (void)hipHostFree(args_host_);
         for (auto& e : ev_)
             if (e) (void)hipEventDestroy(e);
+        for (auto& e : ph_)
+            if (e) (void)hipEventDestroy(e);
     }
 
     im_status init()
@@ -118,6 +122,7 @@ public:
         IMX_HIP(hipMalloc(&args_dev_, args_cap_));
         IMX_HIP(hipHostMalloc(reinterpret_cast<void**>(&args_host_), args_cap_, 0));
         for (auto& e : ev_) IMX_HIP(hipEventCreate(&e));
+        for (auto& e : ph_) IMX_HIP(hipEventCreate(&e));
         // Environment overrides of the default tuning (validated like im_engine_set_tuning).
         im_tuning t = tune_;
         if (const char* v = std::getenv("IMX_GROUP_FIRST")) t.group_first = std::atoi(v);
@@ -193,7 +198,7 @@ public:
             A.release();
             return IM_ENOMEM;
         }
-        if (profiling_level() >= 2 && A.alloc(&q->pc, 1)) {
+        if (profiling_level() >= 2 && (A.alloc(&q->pc, 1) || A.alloc(&q->vstamp, n))) {
             A.release();
             return set_error(IM_ENOMEM, "device allocation failed");
         }
@@ -214,6 +219,7 @@ public:
         if (e == hipSuccess) e = hipMemsetAsync(q->c.lv8, 0, flag_bytes(n), st_);
         if (e == hipSuccess) e = hipMemsetAsync(q->c.touch_stamp, 0, sizeof(uint32_t) * n, st_);
         if (e == hipSuccess && q->pc) e = hipMemsetAsync(q->pc, 0, sizeof(PropCounters), st_);
+        if (e == hipSuccess && q->vstamp) e = hipMemsetAsync(q->vstamp, 0, sizeof(uint32_t) * n, st_);
         if (e == hipSuccess) e = launch_sim_values(seed, J, q->X, st_);
         if (e != hipSuccess) {
             A.release();
@@ -377,6 +383,7 @@ private:
     uint8_t* args_host_ = nullptr;
     size_t args_cap_ = 0, args_off_ = 0;
     hipEvent_t ev_[2 * kMaxRounds] = {};
+    hipEvent_t ph_[4] = {};  // sweep phase start/end, cascade phase start/end
     im_tuning tune_{64, 64, 8, 16};
 };
 
@@ -467,7 +474,9 @@ im_status Engine::step()
                             &q->sw.dense[s & 3],
                             q->sw.conv,
                             &q->sw.rows_changed[s & 3],
-                            q->pc};
+                            q->pc,
+                            q->vstamp,
+                            ++q->prop_launch_id};
                 Launch<PropArgs>& T = (s == 0) ? F : R;
                 const int lanes = propagate_group_size(q->J, s == 0 ? gs_first_ : gs_rest_);
                 T.args.push_back(pa);
@@ -490,7 +499,7 @@ im_status Engine::step()
         Launch<EstArgs> L;
         for (Query* q : ch) {
             L.args.push_back(EstArgs{q->M, q->g->n, q->J, q->Ju, q->Hu});
-            const int64_t rows_per_wg = kWG / row_lanes(q->J);
+            const int64_t rows_per_wg = kWG / row_lanes(q->J) * kRowBatch;
             L.want.push_back(std::min<int64_t>(cus * 16, (q->g->n + rows_per_wg - 1) / rows_per_wg));
         }
         L_est.push_back(std::move(L));
@@ -571,6 +580,8 @@ im_status Engine::step()
 
     // ---- launches, in dependency order
     const bool stats = profiling_level() >= 2;
+    const bool sweeping = !rounds.empty(), cascading = !L_lvl.empty();
+    if (sweeping) IMX_HIP(hipEventRecord(ph_[0], st_));
     for (auto& L : L_fill) IMX_HIP(launch_fill(L.dev, L.B, st_));
     int ne = 0;
     for (auto& R : rounds) {
@@ -582,7 +593,9 @@ im_status Engine::step()
         ++ne;
         for (auto& L : R.mark) IMX_HIP(launch_mark(L.dev, L.B, st_));
     }
+    if (sweeping) IMX_HIP(hipEventRecord(ph_[1], st_));
     for (auto& L : L_est) IMX_HIP(launch_estimate(L.dev, L.B, st_));
+    if (cascading) IMX_HIP(hipEventRecord(ph_[2], st_));
     for (size_t i = 0; i < L_am.size(); ++i) {
         Batch fin{};
         fin.nq = L_am[i].B.nq;
@@ -595,9 +608,13 @@ im_status Engine::step()
         for (auto& L : L_cmp[b]) IMX_HIP(launch_cascade_compact(L.dev, L.B, st_));
     }
     for (auto& L : L_fin) IMX_HIP(launch_cascade_finalize(L.dev, L.B, st_));
+    if (cascading) IMX_HIP(hipEventRecord(ph_[3], st_));
     IMX_HIP(hipMemcpyAsync(status_host_, status_dev_, sizeof(SlotStatus) * cap_, hipMemcpyDeviceToHost, st_));
     IMX_HIP(hipStreamSynchronize(st_));
 
+    float sweep_phase_ms = 0.f, cascade_phase_ms = 0.f;
+    if (sweeping) (void)hipEventElapsedTime(&sweep_phase_ms, ph_[0], ph_[1]);
+    if (cascading) (void)hipEventElapsedTime(&cascade_phase_ms, ph_[2], ph_[3]);
     float prop_ms = 0.f;
     for (int i = 0; i < ne; ++i) {
         float ms = 0.f;
@@ -612,6 +629,7 @@ im_status Engine::step()
         case Stage::Fill:
         case Stage::Sweeps: {
             q->st.prop_kernel_ms += prop_ms / (double)sweep_q.size();
+            q->st.propagate_ms += sweep_phase_ms;
             q->st.prop_launches += nr;
             q->sweep += nr;
             if (S.conv != ~0u) {  // sweep S.conv (0-based) changed nothing: the build is complete
@@ -642,6 +660,7 @@ im_status Engine::step()
         case Stage::Pick:
         case Stage::Levels: {
             q->need_est = false;
+            q->st.cascade_ms += cascade_phase_ms;
             q->level += nr;
             if (S.level_end != ~0u) {  // the cascade ended and was finalized in this tick
                 q->st.cascade_levels += S.level_end - 1u;
@@ -709,9 +728,14 @@ im_status finish_prop_counters(Query* q)
     s.prop_arcs_scanned = (int64_t)c.arcs_scanned;
     s.prop_arcs_active = (int64_t)c.arcs_active;
     s.prop_sectors = (int64_t)c.sectors;
-    s.prop_alg_bytes = 28.0 * c.tasks + 4.0 * c.arcs_scanned + 4.0 * c.arcs_active + 64.0 * c.sectors +
-                       (double)q->J * c.rows_read + (double)c.bytes_written +
-                       (double)((q->g->n + 31) / 32) * 4.0 * 2.0 * (double)s.prop_launches;
+    s.prop_rows_visited = (int64_t)c.rows_visited;
+    s.prop_rows_changed = (int64_t)c.rows_changed;
+    // per sweep: (8 + J) per active row (row bounds, own registers), J per
+    // changed row (stored), 8 + 64 per active arc and sector (head id,
+    // threshold, the head's 64-byte sectors holding live registers)
+    const double J = (double)q->J;
+    s.prop_alg_bytes = (8.0 + J) * (double)c.rows_visited + J * (double)c.rows_changed + 8.0 * (double)c.arcs_active +
+                       64.0 * (double)c.sectors;
     return IM_OK;
 }
 

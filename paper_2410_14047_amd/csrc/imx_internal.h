@@ -87,6 +87,9 @@ __host__ __device__ inline int row_lanes(int J)
     return (c >= 64) ? 64 : (c >= 32) ? 32 : (c >= 16) ? 16 : (c >= 8) ? 8 : 4;
 }
 
+// Rows a lane group of the row-streaming kernels handles together (loads in flight).
+constexpr int kRowBatch = 4;
+
 // Per-vertex flag arrays are padded to whole 16-byte chunks.
 inline int64_t flag_bytes(int64_t n) { return (n + 15) / 16 * 16; }
 
@@ -98,6 +101,8 @@ struct PropCounters {
     unsigned long long arcs_scanned;   // arcs whose head id was read
     unsigned long long arcs_active;    // arcs whose head changed in the previous sweep
     unsigned long long sectors;        // distinct 64-byte sectors of head rows holding live registers
+    unsigned long long rows_visited;   // distinct rows u with at least one arc whose head changed
+    unsigned long long rows_changed;   // distinct rows u that changed
 };
 
 struct ArgmaxScratch {
@@ -149,6 +154,8 @@ struct PropArgs {
     const uint32_t* conv;         // the build converged before this sweep when != ~0u
     unsigned long long* rows_changed;
     PropCounters* stats;          // instrumented variant only
+    uint32_t* vstamp;             // instrumented variant only: [n] last launch id that counted row u
+    uint32_t stamp_id;            // instrumented variant only: id of this launch (increasing)
 };
 
 struct MarkArgs {

@@ -9,6 +9,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 namespace imx {
 
 // ---------------------------------------------------------------------------
@@ -16,15 +18,22 @@ namespace imx {
 
 __device__ __forceinline__ uint32_t rotl32(uint32_t x, int r) { return (x << r) | (x >> (32 - r)); }
 
-__device__ __forceinline__ uint32_t mix_block(uint32_t h, uint32_t k)
+// A key block as the hash mixes it in (depends on the block only).
+__device__ __forceinline__ uint32_t key_block(uint32_t k)
 {
     k *= 0xcc9e2d51u;
     k = rotl32(k, 15);
-    k *= 0x1b873593u;
-    h ^= k;
+    return k * 0x1b873593u;
+}
+
+__device__ __forceinline__ uint32_t mix_key(uint32_t h, uint32_t kk)
+{
+    h ^= kk;
     h = rotl32(h, 13);
     return h * 5u + 0xe6546b64u;
 }
+
+__device__ __forceinline__ uint32_t mix_block(uint32_t h, uint32_t k) { return mix_key(h, key_block(k)); }
 
 __device__ __forceinline__ uint32_t finish(uint32_t h, uint32_t len)
 {
@@ -49,10 +58,11 @@ __device__ __forceinline__ uint32_t rank_prefix(uint64_t seed, uint32_t u)
     return mix_block(mix_block(mix_block(1u, (uint32_t)seed), (uint32_t)(seed >> 32)), u);
 }
 
-// Eq. 3 with the HyperLogLog offset: leading zeros of the j-th hash, plus one.
-__device__ __forceinline__ uint32_t rank_of(uint32_t prefix, uint32_t j)
+// Eq. 3 with the HyperLogLog offset: leading zeros of the j-th hash, plus
+// one; kj = key_block(j).
+__device__ __forceinline__ uint32_t rank_from_key(uint32_t prefix, uint32_t kj)
 {
-    uint32_t g = finish(mix_block(prefix, j), 16u);
+    const uint32_t g = finish(mix_key(prefix, kj), 16u);
     return (g == 0u ? 32u : (uint32_t)__builtin_clz(g)) + 1u;
 }
 
@@ -478,34 +488,47 @@ hipError_t launch_sim_values(uint64_t seed, int J, uint32_t* X, hipStream_t st)
 
 
 
+// Registers of one 16-byte chunk (simulations 16c .. 16c+15) of a row with
+// rank prefix `pre`; covered registers (0 in `old`) stay 0.
+__device__ __forceinline__ uint4 fill_chunk(uint32_t pre, const uint32_t (&kj)[16], uint4 old)
+{
+    const uint32_t ow[4] = {old.x, old.y, old.z, old.w};
+    uint32_t out[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const uint32_t r = ((ow[w] >> (8 * b)) & 0xffu) ? rank_from_key(pre, kj[4 * w + b]) : 0u;
+            o |= r << (8 * b);
+        }
+        out[w] = o;
+    }
+    return make_uint4(out[0], out[1], out[2], out[3]);
+}
+
 __global__ __launch_bounds__(256) void k_fill(const FillArgs* __restrict__ args, Batch B)
 {
     IMX_BATCH_PROLOGUE(FillArgs);
     const int L = row_lanes(a.J);
-    const int lane = lane_id();
-    const int sub = lane % L;
+    const int sub = lane_id() % L;
     const int chunks = a.J / 16;  // per row
     const int64_t rows_per_iter = (int64_t)lg * (blockDim.x / L);
     uint4* M4 = reinterpret_cast<uint4*>(a.M);
+    // key blocks of the lane's first chunk, reused for every row
+    uint32_t kj0[16];
+#pragma unroll
+    for (int b = 0; b < 16; ++b) kj0[b] = key_block((uint32_t)(16 * sub + b));
+    const uint4 all_uncovered = make_uint4(~0u, ~0u, ~0u, ~0u);
     for (int64_t u = lb * (blockDim.x / L) + threadIdx.x / L; u < a.n; u += rows_per_iter) {
         const uint32_t pre = rank_prefix(a.seed, (uint32_t)u);
         uint4* row = M4 + (size_t)u * (size_t)chunks;
-        for (int c = sub; c < chunks; c += L) {
-            const uint4 old = a.first ? make_uint4(~0u, ~0u, ~0u, ~0u) : row[c];
-            const uint32_t ow[4] = {old.x, old.y, old.z, old.w};
-            uint32_t out[4];
+        if (sub < chunks) row[sub] = fill_chunk(pre, kj0, a.first ? all_uncovered : row[sub]);
+        for (int c = sub + L; c < chunks; c += L) {
+            uint32_t kj[16];
 #pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                uint32_t o = 0;
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const uint32_t j = (uint32_t)(16 * c + 4 * w + b);
-                    const uint32_t r = ((ow[w] >> (8 * b)) & 0xffu) ? rank_of(pre, j) : 0u;
-                    o |= r << (8 * b);
-                }
-                out[w] = o;
-            }
-            row[c] = make_uint4(out[0], out[1], out[2], out[3]);
+            for (int b = 0; b < 16; ++b) kj[b] = key_block((uint32_t)(16 * c + b));
+            row[c] = fill_chunk(pre, kj, a.first ? all_uncovered : row[c]);
         }
     }
 }
@@ -643,7 +666,7 @@ __global__ __launch_bounds__(kWG, 6) void k_propagate(const PropArgs* __restrict
     unsigned long long* esec = reinterpret_cast<unsigned long long*>(gbuf + Jw + 5 * GS + 32);  // STATS only
     WaveList chl{wbuf, 0, a.chg_list, a.chg_count, kPropBufCap};
     unsigned long long c_tasks = 0, c_rows = 0, c_wbytes = 0, c_scanned = 0, c_active = 0, c_sectors = 0;
-    unsigned long long c_changed = 0;
+    unsigned long long c_changed = 0, c_visited = 0;
 
     const GraphDev& g = a.g;
     // every task after a fill or after a sweep that changed many rows; else the active list
@@ -718,7 +741,8 @@ __global__ __launch_bounds__(kWG, 6) void k_propagate(const PropArgs* __restrict
             if (lig < 32) dirty[lig] = 0u;
             if (GS == 16) dirty[lig + 16] = 0u;
         }
-        bool touched = false;  // group-uniform: some arc had candidates
+        bool touched = false;      // group-uniform: some arc had candidates
+        bool task_active = false;  // group-uniform: some arc's head changed (instrumented variant)
         for (int c = 0; c < maxch; ++c) {
             const int64_t e = e0 + (int64_t)c * GS + lig;
             int cnt = 0, lo = 0, hi = 0;
@@ -746,6 +770,7 @@ __global__ __launch_bounds__(kWG, 6) void k_propagate(const PropArgs* __restrict
             if (STATS) {
                 c_scanned += (e < e1) ? 1ull : 0ull;
                 c_active += act_arc ? 1ull : 0ull;
+                task_active |= (__ballot(act_arc) & gmask) != 0ull;
             }
             const bool gany = (__ballot(cnt > 0) & gmask) != 0ull;
             if (gany && !touched) {
@@ -890,6 +915,7 @@ __global__ __launch_bounds__(kWG, 6) void k_propagate(const PropArgs* __restrict
             }
         }
         if (first) ++c_changed;
+        if (STATS && task_active && lig == 0 && atomicMax(&a.vstamp[u], a.stamp_id) < a.stamp_id) ++c_visited;
         wl_append_ranges(chl, first ? in_cnt : 0, in_first);
     }
     // per-wave flushes here: measured faster than a workgroup-wide flush,
@@ -906,7 +932,11 @@ __global__ __launch_bounds__(kWG, 6) void k_propagate(const PropArgs* __restrict
         c_scanned = wave_sum_u64(c_scanned);
         c_active = wave_sum_u64(c_active);
         c_sectors = wave_sum_u64(c_sectors);
+        c_visited = wave_sum_u64(c_visited);
+        const unsigned long long chg_tot = wave_sum_u64(c_changed);
         if (lane == 0) {
+            atomicAdd(&a.stats->rows_visited, c_visited);
+            atomicAdd(&a.stats->rows_changed, chg_tot);
             atomicAdd(&a.stats->tasks, c_tasks);
             atomicAdd(&a.stats->rows_read, c_rows);
             atomicAdd(&a.stats->bytes_written, c_wbytes);
@@ -917,15 +947,18 @@ __global__ __launch_bounds__(kWG, 6) void k_propagate(const PropArgs* __restrict
     }
 }
 
+// Launch-configuration caches below are shared by every engine of the
+// process; engines may step on different host threads.
+static std::mutex g_launch_cfg_mutex;
+
 static int cu_count()
 {
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
+    static const int cus = [] {
+        int dev = 0, c = 0;
         (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (cus < 1) cus = 1;
-    }
+        (void)hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
+        return c < 1 ? 1 : c;
+    }();
     return cus;
 }
 
@@ -942,6 +975,7 @@ template <int GS, int DPLG, bool STATS>
 static hipError_t propagate_setup(int J, int* per_cu)
 {
     const size_t lds = propagate_lds<GS, DPLG, STATS>(J);
+    std::lock_guard<std::mutex> lock(g_launch_cfg_mutex);
     static size_t lds_set = 0, attr_set = 0;
     static int cached = 0;
     if (lds_set != lds) {
@@ -1128,29 +1162,43 @@ __global__ __launch_bounds__(kWG) void k_estimate(const EstArgs* __restrict__ ar
     const int lane = lane_id();
     const int sub = lane % L;
     const int chunks = a.J / 16;
-    const int64_t rows_per_wave_iter = 64 / L;
+    const int64_t rpw = 64 / L;  // rows of a wave per batch slot
+    const int64_t per_wave = rpw * kRowBatch;
     const int64_t nw = lg * kWaves;
     const uint4* M4 = reinterpret_cast<const uint4*>(a.M);
     // every lane of a wave runs the same number of iterations (uniform shuffles)
-    for (int64_t vb = (lb * kWaves + (threadIdx.x >> 6)) * rows_per_wave_iter; vb < a.n; vb += nw * rows_per_wave_iter) {
-        const int64_t v = vb + lane / L;
-        uint32_t c = 0;
-        unsigned long long h = 0;
-        if (v < a.n) {
-            const uint4* row = M4 + (size_t)v * (size_t)chunks;
-            for (int k = sub; k < chunks; k += L) {
-                const uint4 q = row[k];
-                est_word(q.x, c, h);
-                est_word(q.y, c, h);
-                est_word(q.z, c, h);
-                est_word(q.w, c, h);
+    for (int64_t vb = (lb * kWaves + (threadIdx.x >> 6)) * per_wave; vb < a.n; vb += nw * per_wave) {
+        uint32_t c[kRowBatch];
+        unsigned long long h[kRowBatch];
+#pragma unroll
+        for (int r = 0; r < kRowBatch; ++r) {
+            c[r] = 0;
+            h[r] = 0;
+        }
+        for (int k = sub; k < chunks; k += L) {
+            uint4 q[kRowBatch];
+#pragma unroll
+            for (int r = 0; r < kRowBatch; ++r) {
+                const int64_t v = vb + r * rpw + lane / L;
+                q[r] = (v < a.n) ? M4[(size_t)v * (size_t)chunks + k] : make_uint4(0u, 0u, 0u, 0u);
+            }
+#pragma unroll
+            for (int r = 0; r < kRowBatch; ++r) {
+                est_word(q[r].x, c[r], h[r]);
+                est_word(q[r].y, c[r], h[r]);
+                est_word(q[r].z, c[r], h[r]);
+                est_word(q[r].w, c[r], h[r]);
             }
         }
-        c = group_sum_u32(c, L);
-        h = group_sum_u64(h, L);
-        if (sub == 0 && v < a.n) {
-            a.Ju[v] = c;
-            a.Hu[v] = h;
+#pragma unroll
+        for (int r = 0; r < kRowBatch; ++r) {
+            const int64_t v = vb + r * rpw + lane / L;
+            const uint32_t cs = group_sum_u32(c[r], L);
+            const unsigned long long hs = group_sum_u64(h[r], L);
+            if (sub == 0 && v < a.n) {
+                a.Ju[v] = cs;
+                a.Hu[v] = hs;
+            }
         }
     }
 }
@@ -1454,6 +1502,7 @@ static size_t level_lds(int J)
 
 hipError_t cascade_level_full_grid(int maxJ, int* grid)
 {
+    std::lock_guard<std::mutex> lock(g_launch_cfg_mutex);
     static size_t lds_set = 0, attr_set = 0;
     static int per_cu = 0;
     const size_t lds = level_lds(maxJ);
@@ -1507,46 +1556,77 @@ hipError_t launch_cascade_compact(const LevelCompactArgs* args, const Batch& B, 
 
 // End of a cascade: markers become 0 in every touched row; Ju/Hu of touched
 // rows are recomputed and T grows by the number of newly covered registers.
+// Clears the cascade markers (>= 64) of one word and adds its uncovered
+// registers to (c, h).
+__device__ __forceinline__ uint32_t fin_word(uint32_t d, uint32_t& c, unsigned long long& h)
+{
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const uint32_t r = (d >> (8 * b)) & 0xffu;
+        if (r >= 64u) {
+            d &= ~(0xffu << (8 * b));
+        } else if (r) {
+            ++c;
+            h += 1ull << (33u - r);
+        }
+    }
+    return d;
+}
+
 __global__ __launch_bounds__(kWG) void k_cascade_finalize(const FinArgs* __restrict__ args, Batch B)
 {
     IMX_BATCH_PROLOGUE(FinArgs);
+    __shared__ unsigned long long s_sum[kWaves];
     const CascadeDev& c = a.c;
-    if (*c.level_end == ~0u) return;  // the cascade is still running
+    if (*c.level_end == ~0u) return;  // the cascade is still running (uniform)
+    const int L = row_lanes(a.J);
     const int lane = lane_id();
-    const int Jw = a.J >> 2;
-    const uint32_t nt = *c.ntouched;
+    const int sub = lane % L;
+    const int chunks = a.J / 16;
+    const int64_t rpw = 64 / L;
+    const int64_t per_wave = rpw * kRowBatch;
     const int64_t nw = lg * kWaves;
+    const int64_t nt = (int64_t)*c.ntouched;
+    uint4* M4 = reinterpret_cast<uint4*>(a.M);
     unsigned long long dT = 0;
-    for (int64_t i = lb * kWaves + (threadIdx.x >> 6); i < (int64_t)nt; i += nw) {
-        const int32_t v = c.touched[i];
-        uint32_t* row = reinterpret_cast<uint32_t*>(a.M + (size_t)v * (size_t)a.J);
-        uint32_t cnt = 0;
-        unsigned long long h = 0;
-        for (int idx = lane; idx < Jw; idx += 64) {
-            uint32_t d = row[idx];
-            const uint32_t o = d;
+    for (int64_t vb = (lb * kWaves + (threadIdx.x >> 6)) * per_wave; vb < nt; vb += nw * per_wave) {
+        int32_t vv[kRowBatch];
+        uint32_t cn[kRowBatch];
+        unsigned long long h[kRowBatch];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const uint32_t r = (d >> (8 * b)) & 0xffu;
-                if (r >= 64u) {
-                    d &= ~(0xffu << (8 * b));
-                } else if (r) {
-                    ++cnt;
-                    h += 1ull << (33u - r);
-                }
-            }
-            if (d != o) row[idx] = d;
+        for (int r = 0; r < kRowBatch; ++r) {
+            const int64_t i = vb + r * rpw + lane / L;
+            vv[r] = (i < nt) ? c.touched[i] : -1;
+            cn[r] = 0;
+            h[r] = 0;
         }
-        cnt = wave_sum_u32(cnt);
-        h = wave_sum_u64(h);
-        if (lane == 0) {
-            const uint32_t old = a.Ju[v];
-            a.Ju[v] = cnt;
-            a.Hu[v] = h;
-            dT += (unsigned long long)(old - cnt);
+        for (int k = sub; k < chunks; k += L) {
+            uint4 q[kRowBatch];
+#pragma unroll
+            for (int r = 0; r < kRowBatch; ++r)
+                q[r] = (vv[r] >= 0) ? M4[(size_t)vv[r] * (size_t)chunks + k] : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+            for (int r = 0; r < kRowBatch; ++r) {
+                if (vv[r] < 0) continue;
+                const uint4 o = q[r];
+                const uint4 nq = make_uint4(fin_word(o.x, cn[r], h[r]), fin_word(o.y, cn[r], h[r]),
+                                            fin_word(o.z, cn[r], h[r]), fin_word(o.w, cn[r], h[r]));
+                if (nq.x != o.x || nq.y != o.y || nq.z != o.z || nq.w != o.w)
+                    M4[(size_t)vv[r] * (size_t)chunks + k] = nq;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kRowBatch; ++r) {
+            const uint32_t cs = group_sum_u32(cn[r], L);
+            const unsigned long long hs = group_sum_u64(h[r], L);
+            if (sub == 0 && vv[r] >= 0) {
+                const uint32_t old = a.Ju[vv[r]];
+                a.Ju[vv[r]] = cs;
+                a.Hu[vv[r]] = hs;
+                dT += (unsigned long long)(old - cs);
+            }
         }
     }
-    __shared__ unsigned long long s_sum[kWaves];
     wg_add_u64(dT, c.T, s_sum);
 }
 

@@ -1,12 +1,19 @@
 """Serving loop: IM queries (graph, J, seed, K) arrive at any time and are
-served by continuous batching on one engine.
+served by continuous batching.
 
 Graphs (one per topology and probability scheme) stay resident on the device.
-A loop thread admits waiting requests in arrival order while their device
-footprint fits the engine's budget and a slot is free, advances every admitted
-query one stage per engine step (their kernels share launches), and completes
-each request's future when its query finishes, releasing its memory for the
-next admissions.  Latency is measured from submit() to completion.
+Each *lane* is one engine with its own stream and loop thread: it admits its
+waiting requests in arrival order while their device footprint fits its
+budget and a slot is free, advances every admitted query one stage per engine
+step (their kernels share launches), and completes each request's future when
+its query finishes, releasing its memory for the next admissions.
+
+Queries are routed to lanes by device footprint (n * J plus work arrays):
+small queries finish in a few hundred launches, large ones in a few
+thousand, and a step lasts as long as its largest query, so keeping them on
+separate engines (whose streams run concurrently on the GPU) stops small
+queries from waiting in lock step behind large ones.  Latency is measured
+from submit() to completion.  Results do not depend on the lane or the mix.
 """
 from __future__ import annotations
 
@@ -14,105 +21,157 @@ import collections
 import threading
 import time
 from concurrent.futures import Future
-from typing import Dict, Optional
+from typing import Dict, List, Optional, Sequence
 
-from .binding import IM_ENOMEM, Engine, Graph, IMError
+from .binding import IM_ENOMEM, Engine, Graph, IMError, im_query_footprint
 
 
-class Server:
-    def __init__(self, graphs: Dict[str, Graph], max_queries: int = 32, hbm_budget_bytes: int = 0,
-                 tuning: Optional[dict] = None, stream=None):
-        self.graphs = dict(graphs)
+class _Lane:
+    def __init__(self, server: "Server", index: int, max_queries: int, hbm_budget_bytes: int,
+                 tuning: Optional[dict], stream):
+        self.server = server
+        self.index = index
         self.engine = Engine(max_queries=max_queries, hbm_budget_bytes=hbm_budget_bytes, stream=stream)
         if tuning:
             self.engine.set_tuning(**tuning)
-        self._wait = collections.deque()
-        self._live = {}
+        self.stream = stream
+        self.wait = collections.deque()
+        self.live = {}
+        self.steps = 0
+        self.thread: Optional[threading.Thread] = None
+
+    def admit(self) -> None:
+        srv = self.server
+        while True:
+            with srv._cv:
+                if not self.wait:
+                    return
+                req = self.wait[0]
+            try:
+                qid = self.engine.submit(srv.graphs[req["graph"]], req["J"], req["seed"], req["K"])
+            except IMError as e:
+                if e.status == IM_ENOMEM and self.live:
+                    return  # wait for memory or a slot to free up
+                with srv._cv:
+                    self.wait.popleft()
+                req["future"].set_exception(e)
+                continue
+            req["t_admit"] = time.perf_counter()
+            with srv._cv:
+                self.wait.popleft()
+            self.live[qid] = req
+
+    def loop(self) -> None:
+        srv = self.server
+        try:
+            while True:
+                with srv._cv:
+                    while not srv._stop and not self.wait and not self.live and srv.error is None:
+                        srv._cv.wait()
+                    if srv.error is not None or (srv._stop and not self.live and not self.wait):
+                        return
+                self.admit()
+                if self.live:
+                    self.engine.step()
+                    self.steps += 1
+                    for qid in self.engine.poll():
+                        req = self.live.pop(qid)
+                        res = self.engine.result(qid)
+                        req["t_done"] = time.perf_counter()
+                        res["latency_s"] = req["t_done"] - req["t_arrival"]
+                        res["queue_s"] = req["t_admit"] - req["t_arrival"]
+                        res["lane"] = self.index
+                        with srv._cv:
+                            srv.completed.append(res)
+                        req["future"].set_result(res)
+        except BaseException as e:  # surface loop failures to every client and to stop()
+            srv._fail(e)
+
+
+class Server:
+    """lanes: footprint bounds in bytes, ascending, one per lane; a query goes
+    to the first lane whose bound is at least its footprint, and to the last
+    lane otherwise (None: one lane).  max_queries and hbm_budget_bytes apply
+    per lane.  `streams` (optional) gives each lane's stream; by default a
+    new torch stream per lane, or `stream` when there is one lane."""
+
+    def __init__(self, graphs: Dict[str, Graph], max_queries: int = 32, hbm_budget_bytes: int = 0,
+                 tuning: Optional[dict] = None, stream=None, lanes: Optional[Sequence[int]] = None,
+                 streams: Optional[Sequence] = None):
+        self.graphs = dict(graphs)
+        self.bounds: List[int] = list(lanes) if lanes else []
+        nl = max(1, len(self.bounds))
+        if streams is None:
+            if nl == 1:
+                streams = [stream]
+            else:
+                import torch
+                streams = [torch.cuda.Stream() for _ in range(nl)]
         self._cv = threading.Condition()
         self._stop = False
-        self._thread: Optional[threading.Thread] = None
-        self.steps = 0
-        self.completed = []
         self.error: Optional[BaseException] = None
+        self.completed = []
+        self.lanes = [_Lane(self, i, max_queries, hbm_budget_bytes, tuning, streams[i]) for i in range(nl)]
+
+    @property
+    def steps(self) -> int:
+        return sum(l.steps for l in self.lanes)
+
+    def _route(self, graph: str, J: int, K: int) -> _Lane:
+        if len(self.lanes) == 1:
+            return self.lanes[0]
+        need = im_query_footprint(self.graphs[graph].handle, J, K)
+        for lane, bound in zip(self.lanes, self.bounds):
+            if need <= bound:
+                return lane
+        return self.lanes[-1]
 
     # -------------------------------------------------------------- client side
     def submit(self, graph: str, J: int, seed: int, K: int) -> Future:
         if graph not in self.graphs:
             raise KeyError(graph)
+        lane = self._route(graph, J, K)
         fut: Future = Future()
         req = dict(graph=graph, J=J, seed=seed, K=K, t_arrival=time.perf_counter(), future=fut)
         with self._cv:
             if self.error is not None:
                 raise RuntimeError("the serving loop has failed") from self.error
-            self._wait.append(req)
-            self._cv.notify()
+            lane.wait.append(req)
+            self._cv.notify_all()
         return fut
 
     def start(self) -> "Server":
-        self._thread = threading.Thread(target=self._loop, name="im-serve", daemon=True)
-        self._thread.start()
+        for lane in self.lanes:
+            lane.thread = threading.Thread(target=lane.loop, name=f"im-serve-{lane.index}", daemon=True)
+            lane.thread.start()
         return self
 
     def stop(self) -> None:
         with self._cv:
             self._stop = True
-            self._cv.notify()
-        if self._thread:
-            self._thread.join()
-        self.engine.free()
+            self._cv.notify_all()
+        for lane in self.lanes:
+            if lane.thread:
+                lane.thread.join()
+        for lane in self.lanes:
+            lane.engine.free()
         if self.error is not None:
             raise self.error
 
-    # -------------------------------------------------------------- loop thread
-    def _admit(self) -> None:
-        while True:
-            with self._cv:
-                if not self._wait:
-                    return
-                req = self._wait[0]
-            try:
-                qid = self.engine.submit(self.graphs[req["graph"]], req["J"], req["seed"], req["K"])
-            except IMError as e:
-                if e.status == IM_ENOMEM and self._live:
-                    return  # wait for memory or a slot to free up
-                with self._cv:
-                    self._wait.popleft()
-                req["future"].set_exception(e)
-                continue
-            req["t_admit"] = time.perf_counter()
-            with self._cv:
-                self._wait.popleft()
-            self._live[qid] = req
-
-    def _loop(self) -> None:
-        try:
-            while True:
-                with self._cv:
-                    while not self._stop and not self._wait and not self._live:
-                        self._cv.wait()
-                    if self._stop and not self._live and not self._wait:
-                        return
-                self._admit()
-                if self._live:
-                    self.engine.step()
-                    self.steps += 1
-                    for qid in self.engine.poll():
-                        req = self._live.pop(qid)
-                        res = self.engine.result(qid)
-                        req["t_done"] = time.perf_counter()
-                        res["latency_s"] = req["t_done"] - req["t_arrival"]
-                        res["queue_s"] = req["t_admit"] - req["t_arrival"]
-                        self.completed.append(res)
-                        req["future"].set_result(res)
-        except BaseException as e:  # surface loop failures to every client and to stop()
-            with self._cv:
+    def _fail(self, e: BaseException) -> None:
+        with self._cv:
+            if self.error is None:
                 self.error = e
-                reqs = list(self._live.values()) + list(self._wait)
-                self._wait.clear()
-            self._live.clear()
-            for req in reqs:
-                if not req["future"].done():
-                    req["future"].set_exception(e)
+            reqs = []
+            for lane in self.lanes:
+                reqs += list(lane.live.values()) + list(lane.wait)
+                lane.wait.clear()
+            self._cv.notify_all()
+        for lane in self.lanes:
+            lane.live.clear()
+        for req in reqs:
+            if not req["future"].done():
+                req["future"].set_exception(e)
 
 
 def replay(server: Server, trace, time_scale: float = 1.0):

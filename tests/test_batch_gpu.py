@@ -144,13 +144,17 @@ def test_server_results_equal_solo(imx):
     for i in range(24):
         t += float(rng.exponential(0.002))
         trace.append((t, names[i % 3], int(rng.choice([64, 256])), int(i), int(rng.integers(2, 8))))
-    srv = serve.Server(graphs, max_queries=6).start()
-    res, makespan = serve.replay(srv, trace)
-    srv.stop()
-    summ = serve.latency_summary(res, makespan)
-    _say(f"[serve] {summ}")
-    for (ta, gname, J, seed, K), r in zip(trace, res):
-        _same(r, _solo(imx, graphs[gname], J, seed, K))
+    solo = [_solo(imx, graphs[gname], J, seed, K) for (ta, gname, J, seed, K) in trace]
+    for lanes in (None, [256 << 10, 1 << 40]):  # one engine; two engines on their own streams
+        srv = serve.Server(graphs, max_queries=6, lanes=lanes).start()
+        res, makespan = serve.replay(srv, trace)
+        srv.stop()
+        summ = serve.latency_summary(res, makespan)
+        _say(f"[serve] lanes={lanes} {summ}")
+        if lanes:
+            assert {r["lane"] for r in res} == {0, 1}
+        for r, s in zip(res, solo):
+            _same(r, s)
 
 
 def test_autotune_keeps_outputs(imx):

@@ -170,3 +170,21 @@ def test_candidate_grid_respects_row_width():
     assert all(c["group_first"] >= 32 and c["group_rest"] >= 32 for c in autotune.candidate_grid(2048))
     assert all(c["group_first"] == 64 for c in autotune.candidate_grid(4096))
     assert {c["group_first"] for c in autotune.candidate_grid(512)} == {16, 32, 64}
+
+
+class _G:
+    def __init__(self, name):
+        self.handle = name
+
+
+def test_server_routes_by_footprint(fake, monkeypatch):
+    made = fake(slots=2)
+    monkeypatch.setattr(serve, "im_query_footprint", lambda h, J, K: J * 1000)
+    srv = serve.Server({"a": _G("A")}, max_queries=2, lanes=[200_000, 10**12], streams=[None, None]).start()
+    futs = [srv.submit("a", J, i, 2) for i, J in enumerate([64, 512, 128, 1024, 192])]
+    res = [f.result(timeout=10) for f in futs]
+    srv.stop()
+    assert [r["lane"] for r in res] == [0, 1, 0, 1, 0]
+    small, large = made
+    assert small.admit_order == [0, 2, 4] and large.admit_order == [1, 3]
+    assert small.freed and large.freed
