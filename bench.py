@@ -111,6 +111,32 @@ def pmc_summary(args):
     print(json.dumps(d))
 
 
+def gather_calibration(mib: int):
+    """Access-rate ceilings of the device memory (libimx_probe.so): random
+    gathers of 16 B (from 64-byte-aligned positions), 64, 128, 256 and 1024 B,
+    a streaming read and a streaming copy, on a MIB MiB buffer; one JSON line."""
+    import ctypes
+
+    import torch
+    torch.cuda.set_device(0)  # the probe library then binds torch's HIP runtime
+    from paper_2410_14047_amd.build import PROBE_LIB
+    if not os.path.exists(PROBE_LIB):
+        raise SystemExit(f"{PROBE_LIB} missing: run __graft_entry__.build()")
+    L = ctypes.CDLL(PROBE_LIB)
+    L.imx_probe_rates.argtypes = [ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]
+    L.imx_probe_rates.restype = ctypes.c_int
+    r = (ctypes.c_double * 7)()
+    rc = L.imx_probe_rates(ctypes.c_uint64(mib << 20), r)
+    if rc != 0:
+        raise SystemExit(f"probe failed with HIP error {rc}")
+    sizes = (16, 64, 128, 256, 1024)
+    out = {"buffer_bytes": mib << 20,
+           "gathers": [{"bytes": b, "per_s": r[i], "lines128_per_s": r[i] * max(1, b // 128),
+                        "GBps_at_gather_size": r[i] * b / 1e9} for i, b in enumerate(sizes)],
+           "stream_read_GBps": r[5] / 1e9, "stream_copy_GBps": r[6] / 1e9}
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(g, w, budget_s: float):
     """The oracle (single thread, as it stands) running full synchronous sweeps
     over a subset of the J simulation columns of the same graph."""
@@ -251,7 +277,8 @@ def served_main(args):
         arr = np.cumsum(rng.exponential(1.0 / lam, size=nq))
         trace = [(float(t), *r) for t, r in zip(arr, reqs)]
         row = {"load": load, "lambda_qps": lam}
-        for mode, mq in (("continuous_batching", args.served_slots), ("serial", 1)):
+        slots = [int(x) for x in args.served_slots.split(",")]
+        for mode, mq in (("continuous_batching", slots), ("serial", 1)):
             lanes = [int(x) << 20 for x in args.served_lanes_mib.split(",")] if mode != "serial" else None
             srv = serve.Server(graphs, max_queries=mq, stream=stream, lanes=lanes).start()
             res, span = serve.replay(srv, trace)
@@ -286,9 +313,12 @@ def main():
     ap.add_argument("--served-scales", default="16,17,18,19,20,21,22,22")
     ap.add_argument("--served-queries", type=int, default=64)
     ap.add_argument("--served-loads", default="0.5,0.8,1.0")
-    ap.add_argument("--served-slots", type=int, default=16, help="queries per lane at once")
+    ap.add_argument("--served-slots", default="16,8,1", help="queries each lane holds at once")
     ap.add_argument("--served-lanes-mib", default="128,1024",
                     help="footprint bounds (MiB) of the serving lanes; larger queries take the last lane")
+    ap.add_argument("--gather-calibration", type=int, default=0, metavar="MIB",
+                    help="only measure random gathers of 64/128/1024-byte rows from a MIB MiB buffer "
+                         "and a streaming copy (the access-rate ceilings of the propagation kernel)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="turn rocprofv3 counter_collection.csv files of this workload and of the copy "
                          "calibration into profiles/propagate_<workload>_pmc.json and print it")
@@ -304,6 +334,8 @@ def main():
         return batched_main(args)
     if args.workload == "served":
         return served_main(args)
+    if args.gather_calibration:
+        return gather_calibration(args.gather_calibration)
     if args.copy_calibration:
         import torch
         nbytes = args.copy_calibration << 20

@@ -25,13 +25,23 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-o", tmp, *SOURCES]
+# Memory access-rate probe used by bench.py's calibration mode (not part of the method).
+PROBE_LIB = os.path.join(PKG, "libimx_probe.so")
+PROBE_SOURCES = [os.path.join(CSRC, "probe.hip")]
+
+
+def _compile(out: str, sources, verbose: bool) -> None:
+    tmp = out + ".tmp"
+    cmd = [HIPCC, *FLAGS, "-o", tmp, *sources]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    _compile(LIB, SOURCES, verbose)
+    _compile(PROBE_LIB, PROBE_SOURCES, verbose)
     return LIB
 
 

@@ -89,18 +89,20 @@ class _Lane:
 
 
 class Server:
-    """lanes: footprint bounds in bytes, ascending, one per lane; a query goes
-    to the first lane whose bound is at least its footprint, and to the last
-    lane otherwise (None: one lane).  max_queries and hbm_budget_bytes apply
-    per lane.  `streams` (optional) gives each lane's stream; by default a
+    """lanes: ascending footprint bounds in bytes of every lane but the last;
+    a query goes to the first lane whose bound is at least its footprint, and
+    to the last lane otherwise (None: one lane).  max_queries (one value, or one per lane)
+    and hbm_budget_bytes apply per lane; a lane of large queries with one slot
+    serves them first come, first served while the other lanes interleave
+    small ones.  `streams` (optional) gives each lane's stream; by default a
     new torch stream per lane, or `stream` when there is one lane."""
 
-    def __init__(self, graphs: Dict[str, Graph], max_queries: int = 32, hbm_budget_bytes: int = 0,
+    def __init__(self, graphs: Dict[str, Graph], max_queries=32, hbm_budget_bytes: int = 0,
                  tuning: Optional[dict] = None, stream=None, lanes: Optional[Sequence[int]] = None,
                  streams: Optional[Sequence] = None):
         self.graphs = dict(graphs)
         self.bounds: List[int] = list(lanes) if lanes else []
-        nl = max(1, len(self.bounds))
+        nl = len(self.bounds) + 1
         if streams is None:
             if nl == 1:
                 streams = [stream]
@@ -111,7 +113,10 @@ class Server:
         self._stop = False
         self.error: Optional[BaseException] = None
         self.completed = []
-        self.lanes = [_Lane(self, i, max_queries, hbm_budget_bytes, tuning, streams[i]) for i in range(nl)]
+        slots = list(max_queries) if isinstance(max_queries, (list, tuple)) else [max_queries] * nl
+        if len(slots) != nl:
+            raise ValueError("max_queries needs one value per lane")
+        self.lanes = [_Lane(self, i, slots[i], hbm_budget_bytes, tuning, streams[i]) for i in range(nl)]
 
     @property
     def steps(self) -> int:

@@ -180,7 +180,7 @@ class _G:
 def test_server_routes_by_footprint(fake, monkeypatch):
     made = fake(slots=2)
     monkeypatch.setattr(serve, "im_query_footprint", lambda h, J, K: J * 1000)
-    srv = serve.Server({"a": _G("A")}, max_queries=2, lanes=[200_000, 10**12], streams=[None, None]).start()
+    srv = serve.Server({"a": _G("A")}, max_queries=2, lanes=[200_000], streams=[None, None]).start()
     futs = [srv.submit("a", J, i, 2) for i, J in enumerate([64, 512, 128, 1024, 192])]
     res = [f.result(timeout=10) for f in futs]
     srv.stop()
