@@ -137,25 +137,46 @@ def gather_calibration(mib: int):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(g, w, budget_s: float):
-    """The oracle (single thread, as it stands) running full synchronous sweeps
-    over a subset of the J simulation columns of the same graph."""
+def cpu_info():
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model
+
+
+def cpu_baseline(g, w, budget_s: float, threads: int):
+    """The oracle, as it stands, running full synchronous sweeps over a sample
+    of the J simulation columns of the same graph; the columns are split over
+    `threads` host threads, each running the oracle on its own columns
+    (simulations are independent)."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import numpy as np
     import oracle
     J, seed = w["J"], w["sseed"]
     t0 = time.perf_counter()
     oracle.sweeps_sample(g, J, seed, np.arange(16, dtype=np.int32), 1)
     per_col_sweep = max((time.perf_counter() - t0) / 16, 1e-4)
-    sweeps = 2
-    S = int(max(1, min(J, budget_s / per_col_sweep / sweeps)))
+    per_thread = int(max(1, min(J // threads if J >= threads else 1, budget_s / per_col_sweep / 2)))
+    S = min(J, per_thread * threads)
+    # more sweeps when every column fits in the budget (at most 8)
+    sweeps = int(max(2, min(8, budget_s / (per_col_sweep * max(1, S // threads)))))
     sims = np.linspace(0, J - 1, S).astype(np.int32)
+    parts = [p for p in np.array_split(sims, threads) if len(p)]
     t0 = time.perf_counter()
-    oracle.sweeps_sample(g, J, seed, sims, sweeps)
+    with ThreadPoolExecutor(len(parts)) as ex:
+        list(ex.map(lambda p: oracle.sweeps_sample(g, J, seed, p, sweeps), parts))
     dt = time.perf_counter() - t0
     rate = S * g.m * sweeps / dt
-    return {"value": rate, "unit": "register updates/s", "cores": 1, "kind": "oracle",
+    return {"value": rate, "unit": "register updates/s", "cores": len(parts), "kind": "oracle",
+            "cpu": cpu_info(), "host_cpus": os.cpu_count(),
             "sample": f"{sweeps} synchronous sweeps (from fill) over {S} of {J} simulation columns, "
-                      f"all {g.m} arcs, single thread; {dt:.1f} s"}
+                      f"all {g.m} arcs, {len(parts)} threads over disjoint columns; {dt:.1f} s"}
 
 
 def batched_main(args):
@@ -306,7 +327,9 @@ def main():
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + ["batched64", "served"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-roofline", action="store_true", help="skip the instrumented byte-count pass")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work in cpu_baseline")
+    ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1),
+                    help="host threads of the cpu_baseline oracle run (default: all cores, at most 16)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (calibrates rocprofv3 "
                          "FETCH_SIZE / WRITE_SIZE against a kernel of known traffic)")
@@ -358,13 +381,20 @@ def main():
           file=sys.stderr, flush=True)
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t_load = time.perf_counter()
     G = imx.Graph.from_graphgen(g, stream=stream)
+    torch.cuda.synchronize()
+    load_ms = (time.perf_counter() - t_load) * 1e3
     J, K, seed = w["J"], w["K"], w["sseed"]
+    step_ms = []
 
     def step():
+        t = time.perf_counter()
         S = imx.Sketch(G, J, seed, stream=stream)
         r = S.select(K)
         S.free()
+        step_ms.append((time.perf_counter() - t) * 1e3)
         return r
 
     for i in range(args.warmup):
@@ -373,6 +403,7 @@ def main():
               flush=True)
 
     torch.cuda.synchronize()
+    step_ms.clear()
     t_start = time.perf_counter()
     results = [step() for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -400,6 +431,8 @@ def main():
         "config": {"workload": args.workload, "n": g.n, "m": g.m, "J": J, "K": K, "p_scheme": w["scheme"],
                    "graph_seed": w["gseed"], "sketch_seed": seed, "parallelism": "single GPU"},
         "k_seed_wall_ms": wall / args.steps * 1e3,
+        "k_seed_wall_ms_median": float(sorted(step_ms)[len(step_ms) // 2]),
+        "graph_load_ms": load_ms,
         "sweeps_per_step": sweeps / args.steps,
         "rebuilds_per_step": results[0]["stats"]["rebuilds"],
         "spread": results[0]["spread"],
@@ -431,8 +464,7 @@ def main():
               file=sys.stderr, flush=True)
 
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(g, w, args.cpu_budget)
-        out["cpu_baseline"]["cores"] = 1
+        out["cpu_baseline"] = cpu_baseline(g, w, args.cpu_budget, args.cpu_threads)
     G.free()
     print(json.dumps(out), flush=True)
 

@@ -84,6 +84,24 @@ const char* im_last_error(void);
 im_status im_version(int32_t* major, int32_t* minor);
 
 /*
+ * Device memory hooks, so that a host framework (for example PyTorch's caching
+ * allocator) owns the device memory of the library (the problem statement's
+ * inputs and the method's state are otherwise allocated with hipMalloc).
+ *   alloc(bytes, ctx)  returns a device pointer aligned to at least 16 bytes,
+ *                      or NULL when it cannot (the calling im_* function then
+ *                      fails with IM_ENOMEM and changes nothing);
+ *   free_(ptr, ctx)    returns a pointer alloc gave.
+ * Process-wide; applies to graphs, sketches and engines created afterwards.
+ * Every buffer is returned to the hooks that allocated it, also after the
+ * hooks change.  Both NULL restores hipMalloc / hipFree.  Errors: IM_EINVAL
+ * when exactly one of the two is NULL.  The hooks may be called from any
+ * thread that calls into the library.
+ */
+typedef void* (*im_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*im_free_fn)(void* ptr, void* ctx);
+im_status im_set_allocator(im_alloc_fn alloc, im_free_fn free_, void* ctx);
+
+/*
  * Process-wide measurement switch for sketches built afterwards:
  *   0  per-launch propagation kernel times only (HIP events; the default),
  *   2  additionally run the instrumented propagation kernel, which counts the

@@ -60,11 +60,15 @@ EXPORTS = [
     "im_sketch_stats", "im_sketch_sim_values", "im_sketch_free",
     "im_engine_create", "im_engine_submit", "im_engine_step", "im_engine_poll", "im_engine_result",
     "im_engine_info", "im_query_footprint", "im_engine_free", "im_select_seeds_batch",
-    "im_engine_set_tuning", "im_engine_get_tuning",
+    "im_engine_set_tuning", "im_engine_get_tuning", "im_set_allocator",
 ]
 _VOID = ("im_last_error", "im_graph_free", "im_sketch_free", "im_engine_free", "im_query_footprint")
 
 _lib = None
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_hooks = None  # keeps the active ctypes callbacks alive
 
 
 def lib() -> ctypes.CDLL:
@@ -90,6 +94,7 @@ def lib() -> ctypes.CDLL:
         L.im_last_error.restype = ctypes.c_char_p
         L.im_version.argtypes = [P, P]
         L.im_set_profiling.argtypes = [i32]
+        L.im_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, P]
         L.im_graph_load.argtypes = [i64, i64, P, P, P, P, P]
         L.im_graph_info.argtypes = [P, P, P]
         L.im_graph_free.argtypes = [P]
@@ -158,6 +163,51 @@ def im_graph_load(n: int, rowptr: np.ndarray, col: np.ndarray, p: np.ndarray, st
 
 def im_set_profiling(level: int) -> None:
     _check(lib().im_set_profiling(level))
+
+
+def im_set_allocator(alloc=None, free=None) -> None:
+    """Install device memory hooks: alloc(nbytes) -> int device pointer (0 on
+    failure), free(ptr) -> None.  Both None restores hipMalloc/hipFree."""
+    global _hooks
+    if (alloc is None) != (free is None):
+        raise ValueError("give both hooks or neither")
+    if alloc is None:
+        _check(lib().im_set_allocator(_ALLOC_FN(), _FREE_FN(), None))
+        _hooks = None
+        return
+
+    def _a(nbytes, ctx):
+        try:
+            return int(alloc(int(nbytes))) or None
+        except Exception:  # an exception must not cross the C boundary
+            return None
+
+    def _f(ptr, ctx):
+        try:
+            free(int(ptr))
+        except Exception:
+            pass
+
+    hooks = (_ALLOC_FN(_a), _FREE_FN(_f))
+    _check(lib().im_set_allocator(hooks[0], hooks[1], None))
+    _hooks = hooks
+
+
+def use_torch_allocator(enable: bool = True, device: int = 0) -> None:
+    """Make PyTorch's caching allocator own the library's device memory (graphs,
+    sketches and engines created afterwards); enable=False restores hipMalloc."""
+    if not enable:
+        im_set_allocator()
+        return
+    import torch
+
+    def _alloc(nbytes):
+        return torch.cuda.caching_allocator_alloc(nbytes, device=device)
+
+    def _free(ptr):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    im_set_allocator(_alloc, _free)
 
 
 def im_graph_free(g) -> None:

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -48,6 +49,42 @@ im_status set_error(im_status st, const std::string& msg)
 
 int profiling_level() { return g_profiling.load(); }
 
+namespace {
+std::mutex g_alloc_mutex;
+DeviceAllocator g_alloc;
+}  // namespace
+
+DeviceAllocator current_allocator()
+{
+    std::lock_guard<std::mutex> lock(g_alloc_mutex);
+    return g_alloc;
+}
+
+hipError_t device_alloc(size_t bytes, DeviceBlock* out)
+{
+    out->from = current_allocator();
+    out->ptr = nullptr;
+    if (out->from.alloc) {
+        out->ptr = out->from.alloc(bytes, out->from.ctx);
+        // blocks serve 16-byte vector loads
+        if (out->ptr && (reinterpret_cast<uintptr_t>(out->ptr) & 15u)) {
+            out->from.free_(out->ptr, out->from.ctx);
+            out->ptr = nullptr;
+        }
+        return out->ptr ? hipSuccess : hipErrorOutOfMemory;
+    }
+    return hipMalloc(&out->ptr, bytes);
+}
+
+void device_free(const DeviceBlock& b)
+{
+    if (!b.ptr) return;
+    if (b.from.free_)
+        b.from.free_(b.ptr, b.from.ctx);
+    else
+        (void)hipFree(b.ptr);
+}
+
 }  // namespace imx
 
 using imx::set_error;
@@ -60,6 +97,14 @@ im_status im_version(int32_t* major, int32_t* minor)
 {
     if (major) *major = 0;
     if (minor) *minor = 1;
+    return IM_OK;
+}
+
+im_status im_set_allocator(im_alloc_fn alloc, im_free_fn free_, void* ctx)
+{
+    if ((alloc == nullptr) != (free_ == nullptr)) return set_error(IM_EINVAL, "set both hooks or neither");
+    std::lock_guard<std::mutex> lock(imx::g_alloc_mutex);
+    imx::g_alloc = imx::DeviceAllocator{alloc, free_, alloc ? ctx : nullptr};
     return IM_OK;
 }
 
@@ -146,8 +191,9 @@ im_status im_graph_load(int64_t n, int64_t m, const int64_t* rowptr_host, const 
     g->in_split = in_split;
     g->n_in_tasks = (int64_t)itv.size();
     float* p_dev = nullptr;
+    imx::Arena tmp;  // probabilities, freed after the thresholds are computed
     auto cleanup = [&](im_status st, const std::string& msg) {
-        if (p_dev) (void)hipFree(p_dev);
+        tmp.release();
         g->arena.release();
         delete g;
         return set_error(st, msg);
@@ -156,7 +202,7 @@ im_status im_graph_load(int64_t n, int64_t m, const int64_t* rowptr_host, const 
     if (A.alloc(&g->rowptr, n + 1) || A.alloc(&g->col, m) || A.alloc(&g->W, m) || A.alloc(&g->task_u, tu.size()) ||
         A.alloc(&g->task_e0, te.size()) || A.alloc(&g->task_len, tl.size()) || A.alloc(&g->task_start, n + 1) || A.alloc(&g->in_rowptr, n + 1) ||
         A.alloc(&g->in_col, m) || A.alloc(&g->in_task_v, itv.size()) || A.alloc(&g->in_task_e0, ite.size()) ||
-        A.alloc(&g->in_task_start, n + 1) || hipMalloc(&p_dev, std::max<size_t>(m * sizeof(float), 1)) != hipSuccess)
+        A.alloc(&g->in_task_start, n + 1) || tmp.alloc(&p_dev, (size_t)m))
         return cleanup(IM_ENOMEM, "device allocation failed");
     hipStream_t st = g->stream;
     hipError_t e = hipMemcpyAsync(g->rowptr, rowptr_host, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, st);
@@ -183,7 +229,7 @@ im_status im_graph_load(int64_t n, int64_t m, const int64_t* rowptr_host, const 
     if (e == hipSuccess) e = imx::launch_thresholds(p_dev, g->W, m, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return cleanup(IM_EDEVICE, std::string("graph upload: ") + hipGetErrorString(e));
-    (void)hipFree(p_dev);
+    tmp.release();
     p_dev = nullptr;
     *out = g;
     return IM_OK;

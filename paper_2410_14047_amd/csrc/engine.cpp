@@ -93,10 +93,10 @@ public:
     Engine(hipStream_t st, int capacity, size_t budget) : st_(st), cap_(capacity), budget_(budget) {}
     ~Engine()
     {
+        (void)hipStreamSynchronize(st_);  // no kernel may still use the buffers below
         for (Query* q : slots_)
             if (q) release(q);
-        if (status_dev_) (void)hipFree(status_dev_);
-        if (args_dev_) (void)hipFree(args_dev_);
+        bufs_.release();
         if (status_host_) (void)hipHostFree(status_host_);
         if (args_host_) (void)hipHostFree(args_host_);
         for (auto& e : ev_)
@@ -109,7 +109,7 @@ public:
     {
         if (cap_ < 1) return set_error(IM_EINVAL, "engine capacity must be >= 1");
         slots_.assign(cap_, nullptr);
-        IMX_HIP(hipMalloc(&status_dev_, sizeof(SlotStatus) * cap_));
+        IMX_HIP(bufs_.alloc(&status_dev_, (size_t)cap_));
         IMX_HIP(hipMemsetAsync(status_dev_, 0, sizeof(SlotStatus) * cap_, st_));
         IMX_HIP(hipHostMalloc(reinterpret_cast<void**>(&status_host_), sizeof(SlotStatus) * cap_, 0));
         // argument records of one tick: at most kMaxRounds x (prep, propagate,
@@ -119,7 +119,7 @@ public:
         static_assert(sizeof(LevelArgs) + sizeof(LevelCompactArgs) <= 3 * 256, "level records");
         const size_t chunks = ((size_t)cap_ + kMaxBatch - 1) / kMaxBatch;
         args_cap_ = (size_t)cap_ * (kMaxRounds * 3 * 256 + 2048) + chunks * (kMaxRounds * 5 + 16) * 256;
-        IMX_HIP(hipMalloc(&args_dev_, args_cap_));
+        IMX_HIP(bufs_.alloc(&args_dev_, args_cap_));
         IMX_HIP(hipHostMalloc(reinterpret_cast<void**>(&args_host_), args_cap_, 0));
         for (auto& e : ev_) IMX_HIP(hipEventCreate(&e));
         for (auto& e : ph_) IMX_HIP(hipEventCreate(&e));
@@ -377,6 +377,7 @@ private:
     size_t used_ = 0;
     int64_t next_id_ = 1;
     std::vector<Query*> slots_;
+    Arena bufs_;  // the engine's own device buffers (status records, argument records)
     SlotStatus* status_dev_ = nullptr;
     SlotStatus* status_host_ = nullptr;
     uint8_t* args_dev_ = nullptr;

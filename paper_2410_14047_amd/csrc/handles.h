@@ -25,27 +25,46 @@ int profiling_level();
             return ::imx::set_error(IM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));       \
     } while (0)
 
-// Device allocations of one handle; released together.
+// Device memory source: hipMalloc/hipFree, or the hooks of im_set_allocator.
+struct DeviceAllocator {
+    im_alloc_fn alloc = nullptr;
+    im_free_fn free_ = nullptr;
+    void* ctx = nullptr;
+};
+
+// The hooks in effect now (a snapshot; im_set_allocator may change them).
+DeviceAllocator current_allocator();
+
+// One device buffer and the source that must free it.
+struct DeviceBlock {
+    void* ptr;
+    DeviceAllocator from;
+};
+
+hipError_t device_alloc(size_t bytes, DeviceBlock* out);
+void device_free(const DeviceBlock& b);
+
+// Device allocations of one handle; released together, each to its source.
 struct Arena {
-    std::vector<void*> ptrs;
+    std::vector<DeviceBlock> blocks;
     size_t bytes = 0;
     template <class T>
     hipError_t alloc(T** p, size_t count)
     {
-        void* q = nullptr;
+        DeviceBlock b{};
         const size_t nb = std::max<size_t>(count * sizeof(T), 1);
-        hipError_t e = hipMalloc(&q, nb);
+        hipError_t e = device_alloc(nb, &b);
         if (e == hipSuccess) {
-            ptrs.push_back(q);
+            blocks.push_back(b);
             bytes += nb;
-            *p = static_cast<T*>(q);
+            *p = static_cast<T*>(b.ptr);
         }
         return e;
     }
     void release()
     {
-        for (void* p : ptrs) (void)hipFree(p);
-        ptrs.clear();
+        for (const DeviceBlock& b : blocks) device_free(b);
+        blocks.clear();
         bytes = 0;
     }
 };

@@ -83,3 +83,18 @@ def test_no_silent_cpu_fallback(imx):
 
 def test_footprint_of_null_graph_is_zero(imx):
     assert imx.lib().im_query_footprint(None, 64, 1) == 0
+
+
+def test_set_allocator_arguments(imx):
+    import ctypes
+    from paper_2410_14047_amd import binding
+    L = imx.lib()
+    null_a, null_f = binding._ALLOC_FN(), binding._FREE_FN()
+    hook_a = binding._ALLOC_FN(lambda n, c: None)
+    hook_f = binding._FREE_FN(lambda p, c: None)
+    assert L.im_set_allocator(hook_a, null_f, None) == 1  # IM_EINVAL: one hook only
+    assert L.im_set_allocator(null_a, hook_f, None) == 1
+    assert L.im_set_allocator(null_a, null_f, None) == 0  # back to hipMalloc
+    with pytest.raises(ValueError):
+        imx.im_set_allocator(lambda n: 0, None)
+    imx.im_set_allocator()  # no-op reset
