@@ -210,15 +210,18 @@ def batched_main(args):
     # autotune on every 8th query (not timed)
     tuned = autotune.autotune(queries[::8], candidates=[
         dict(group_first=gf, group_rest=gr, rounds_per_step=r, dense_div=16)
-        for gf in (32, 64) for gr in (16, 64) for r in (2, 4)], stream=stream)
+        for gf in (32, 64) for gr in (16, 32, 64) for r in (4, 8, 16)], stream=stream)
     tuning = tuned["best"]
     print(f"[bench] tuning {tuning}", file=sys.stderr, flush=True)
 
-    def run_batched():
+    counters = {}
+
+    def run_batched(graphs=0):
         E = imx.Engine(max_queries=64, stream=stream)
-        E.set_tuning(**tuning)
+        E.set_tuning(**{**tuning, "use_graphs": graphs})
         ids = [E.submit(*q) for q in queries]
         res = E.run()
+        counters["graphs" if graphs else "direct"] = E.counters()
         E.free()
         return [res[i] for i in ids]
 
@@ -232,7 +235,9 @@ def batched_main(args):
 
     run_batched()  # warm-up
     times = {}
-    for name, fn in (("batched", run_batched), ("one_query_per_launch", run_single)):
+    run_batched(1)  # warm-up of graph mode
+    for name, fn in (("batched", run_batched), ("batched_hip_graphs", lambda: run_batched(1)),
+                     ("one_query_per_launch", run_single)):
         torch.cuda.synchronize()
         t = time.perf_counter()
         res = fn()
@@ -240,14 +245,16 @@ def batched_main(args):
         times[name] = (time.perf_counter() - t, res)
         print(f"[bench] {name}: {times[name][0]:.3f} s", file=sys.stderr, flush=True)
     a, b = times["batched"][1], times["one_query_per_launch"][1]
-    for ra, rb in zip(a, b):
-        assert list(ra["seeds"]) == list(rb["seeds"]) and list(ra["T"]) == list(rb["T"]), "outputs differ"
+    for other in (b, times["batched_hip_graphs"][1]):
+        for ra, rb in zip(a, other):
+            assert list(ra["seeds"]) == list(rb["seeds"]) and list(ra["T"]) == list(rb["T"]), "outputs differ"
     upd = sum(J * G.m * r["stats"]["total_sweeps"] for G, r in zip(Gs, a))
     tb, ts = times["batched"][0], times["one_query_per_launch"][0]
     print(json.dumps({
         "metric": "batched IM queries: wall time of 64 queries (and register updates/s)",
         "value": 64 / tb, "unit": "queries/s", "n_gpus": 1, "higher_is_better": True,
-        "batched_s": tb, "one_query_per_launch_s": ts, "speedup": ts / tb,
+        "batched_s": tb, "batched_hip_graphs_s": times["batched_hip_graphs"][0], "one_query_per_launch_s": ts,
+        "speedup": ts / tb, "engine_counters": counters,
         "register_updates_per_s": upd / tb, "identical_outputs": True, "tuning": tuning,
         "config": {"workload": "batched64_rmat12-18_ba10k-200k_wc_J256_K20", "graphs": 64,
                    "arcs": int(sum(g.m for g in gs)), "J": J, "K": K},

@@ -222,19 +222,28 @@ im_status im_engine_create(int32_t max_queries, uint64_t hbm_budget_bytes, void*
  *   rounds_per_step          sweeps / cascade levels launched per step (1..16);
  *   dense_div                a sweep visits every task instead of an active
  *                            list when more than n / dense_div rows changed in
- *                            the previous sweep (>= 1).
- * Defaults: 64, 64, 8, 16; the environment variables IMX_GROUP_FIRST,
- * IMX_GROUP, IMX_ROUNDS and IMX_DENSE_DIV override them at engine creation
- * (an out-of-range value makes creation fail with IM_EINVAL). */
+ *                            the previous sweep (>= 1);
+ *   use_graphs               1: a step's launches are captured in a HIP graph
+ *                            the first time their structure (kernels, grids,
+ *                            query split) occurs and replayed while it repeats
+ *                            (no per-launch kernel times then); 0: direct
+ *                            launches.
+ * Defaults: 64, 64, 8, 16, 0; the environment variables IMX_GROUP_FIRST,
+ * IMX_GROUP, IMX_ROUNDS, IMX_DENSE_DIV and IMX_GRAPHS override them at engine
+ * creation (an out-of-range value makes creation fail with IM_EINVAL). */
 typedef struct im_tuning {
     int32_t group_first;
     int32_t group_rest;
     int32_t rounds_per_step;
     int32_t dense_div;
+    int32_t use_graphs;
 } im_tuning;
 
 im_status im_engine_set_tuning(im_engine* e, const im_tuning* t);
 im_status im_engine_get_tuning(const im_engine* e, im_tuning* t);
+
+/* Steps taken, graphs captured and graph replays of an engine (diagnostics). */
+im_status im_engine_counters(const im_engine* e, int64_t* steps, int64_t* graphs_built, int64_t* graph_replays);
 
 /* Admit a query; *query_id receives its id.  Errors: IM_EINVAL (J, K, graph),
  * IM_ENOMEM (no free slot or budget exceeded; nothing changed), IM_EDEVICE. */

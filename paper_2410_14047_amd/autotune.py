@@ -15,7 +15,7 @@ from typing import Iterable, Optional
 
 from .binding import Engine, Graph
 
-DEFAULT = dict(group_first=64, group_rest=64, rounds_per_step=8, dense_div=16)
+DEFAULT = dict(group_first=64, group_rest=64, rounds_per_step=8, dense_div=16, use_graphs=0)
 
 
 def candidate_grid(J_max: int) -> list:

@@ -60,7 +60,7 @@ EXPORTS = [
     "im_sketch_stats", "im_sketch_sim_values", "im_sketch_free",
     "im_engine_create", "im_engine_submit", "im_engine_step", "im_engine_poll", "im_engine_result",
     "im_engine_info", "im_query_footprint", "im_engine_free", "im_select_seeds_batch",
-    "im_engine_set_tuning", "im_engine_get_tuning", "im_set_allocator",
+    "im_engine_set_tuning", "im_engine_get_tuning", "im_set_allocator", "im_engine_counters",
 ]
 _VOID = ("im_last_error", "im_graph_free", "im_sketch_free", "im_engine_free", "im_query_footprint")
 
@@ -94,6 +94,7 @@ def lib() -> ctypes.CDLL:
         L.im_last_error.restype = ctypes.c_char_p
         L.im_version.argtypes = [P, P]
         L.im_set_profiling.argtypes = [i32]
+        L.im_engine_counters.argtypes = [P, P, P, P]
         L.im_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, P]
         L.im_graph_load.argtypes = [i64, i64, P, P, P, P, P]
         L.im_graph_info.argtypes = [P, P, P]
@@ -335,7 +336,8 @@ class Sketch:
 
 class im_tuning(ctypes.Structure):
     _fields_ = [("group_first", ctypes.c_int32), ("group_rest", ctypes.c_int32),
-                ("rounds_per_step", ctypes.c_int32), ("dense_div", ctypes.c_int32)]
+                ("rounds_per_step", ctypes.c_int32), ("dense_div", ctypes.c_int32),
+                ("use_graphs", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -387,14 +389,19 @@ class Engine:
         return dict(seeds=seeds, spread=spread.value, est=est, T=T, stats=stats.as_dict())
 
     def set_tuning(self, group_first: int = 64, group_rest: int = 64, rounds_per_step: int = 8,
-                   dense_div: int = 16) -> None:
-        t = im_tuning(group_first, group_rest, rounds_per_step, dense_div)
+                   dense_div: int = 16, use_graphs: int = 0) -> None:
+        t = im_tuning(group_first, group_rest, rounds_per_step, dense_div, int(use_graphs))
         _check(lib().im_engine_set_tuning(self.handle, ctypes.byref(t)))
 
     def get_tuning(self) -> dict:
         t = im_tuning()
         _check(lib().im_engine_get_tuning(self.handle, ctypes.byref(t)))
         return t.as_dict()
+
+    def counters(self) -> dict:
+        st, gb, gr = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().im_engine_counters(self.handle, ctypes.byref(st), ctypes.byref(gb), ctypes.byref(gr)))
+        return dict(steps=st.value, graphs_built=gb.value, graph_replays=gr.value)
 
     def info(self) -> dict:
         nq, nr = ctypes.c_int32(), ctypes.c_int32()

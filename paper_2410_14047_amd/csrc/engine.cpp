@@ -94,6 +94,11 @@ public:
     ~Engine()
     {
         (void)hipStreamSynchronize(st_);  // no kernel may still use the buffers below
+        drop_graph();
+        if (gstream_) {
+            (void)hipStreamSynchronize(gstream_);
+            (void)hipStreamDestroy(gstream_);
+        }
         for (Query* q : slots_)
             if (q) release(q);
         bufs_.release();
@@ -129,6 +134,7 @@ public:
         if (const char* v = std::getenv("IMX_GROUP")) t.group_rest = std::atoi(v);
         if (const char* v = std::getenv("IMX_ROUNDS")) t.rounds_per_step = std::atoi(v);
         if (const char* v = std::getenv("IMX_DENSE_DIV")) t.dense_div = std::atoi(v);
+        if (const char* v = std::getenv("IMX_GRAPHS")) t.use_graphs = std::atoi(v);
         if (set_tuning(t) != IM_OK) return IM_EINVAL;
         IMX_HIP(hipStreamSynchronize(st_));
         return IM_OK;
@@ -324,12 +330,18 @@ public:
     {
         auto ok_gs = [](int v) { return v == 16 || v == 32 || v == 64; };
         if (!ok_gs(t.group_first) || !ok_gs(t.group_rest) || t.rounds_per_step < 1 ||
-            t.rounds_per_step > kMaxRounds || t.dense_div < 1)
+            t.rounds_per_step > kMaxRounds || t.dense_div < 1 || (t.use_graphs != 0 && t.use_graphs != 1))
             return set_error(IM_EINVAL, "tuning out of range");
         tune_ = t;
         return IM_OK;
     }
     const im_tuning& tuning() const { return tune_; }
+    void counters(int64_t* steps, int64_t* built, int64_t* replays) const
+    {
+        if (steps) *steps = steps_;
+        if (built) *built = graphs_built_;
+        if (replays) *replays = graph_replays_;
+    }
 
 private:
     // Argument records of one tick are packed into a pinned host buffer and
@@ -385,7 +397,21 @@ private:
     size_t args_cap_ = 0, args_off_ = 0;
     hipEvent_t ev_[2 * kMaxRounds] = {};
     hipEvent_t ph_[4] = {};  // sweep phase start/end, cascade phase start/end
-    im_tuning tune_{64, 64, 8, 16};
+    // graph mode: the instantiated graph of the last captured tick structure
+    hipGraph_t graph_ = nullptr;
+    hipGraphExec_t graph_exec_ = nullptr;
+    std::vector<int64_t> graph_key_;
+    hipStream_t gstream_ = nullptr;  // private stream for graphs when the engine's stream is the null stream
+    int64_t graphs_built_ = 0, graph_replays_ = 0, steps_ = 0;
+    void drop_graph()
+    {
+        if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
+        if (graph_) (void)hipGraphDestroy(graph_);
+        graph_exec_ = nullptr;
+        graph_ = nullptr;
+        graph_key_.clear();
+    }
+    im_tuning tune_{64, 64, 8, 16, 0};
 };
 
 im_status Engine::step()
@@ -396,6 +422,7 @@ im_status Engine::step()
                   q->stage == Stage::Pick || q->stage == Stage::Levels))
             act.push_back(q);
     if (act.empty()) return IM_OK;
+    ++steps_;
     const int cus = device_cu_count();
     const int nr = tune_.rounds_per_step;
     const int gs_first_ = tune_.group_first, gs_rest_ = tune_.group_rest;
@@ -554,70 +581,127 @@ im_status Engine::step()
         L_fin.push_back(std::move(L));
     }
 
-    // ---- stage argument records, one copy
-    auto finish = [&](auto& L, int64_t cap) -> bool {
+    // ---- stage argument records, one copy; the tick's launch structure
+    // (kinds, grids, batch splits, record offsets) forms its graph key
+    std::vector<int64_t> key;
+    auto finish = [&](int kind, auto& L, int64_t cap) -> bool {
         L.dev = stage_args(L.args);
         L.B = make_batch(L.want, cap);
+        key.push_back(kind);
+        key.push_back(L.dev ? reinterpret_cast<const uint8_t*>(L.dev) - args_dev_ : -1);
+        key.push_back(L.maxJ);
+        key.push_back(L.B.nq);
+        for (int i = 0; i <= L.B.nq; ++i) key.push_back(L.B.wg0[i]);
         return L.dev != nullptr;
     };
     bool ok = true;
-    for (auto& L : L_fill) ok &= finish(L, 0);
+    for (auto& L : L_fill) ok &= finish(0, L, 0);
     for (auto& R : rounds) {
-        for (auto& L : R.prep) ok &= finish(L, 0);
-        for (auto& L : R.prop_first) ok &= finish(L, full_first);
-        for (auto& L : R.prop_rest) ok &= finish(L, full_rest);
-        for (auto& L : R.mark) ok &= finish(L, (int64_t)cus * 4);
+        for (auto& L : R.prep) ok &= finish(1, L, 0);
+        for (auto& L : R.prop_first) ok &= finish(2, L, full_first);
+        for (auto& L : R.prop_rest) ok &= finish(3, L, full_rest);
+        for (auto& L : R.mark) ok &= finish(4, L, (int64_t)cus * 4);
     }
-    for (auto& L : L_est) ok &= finish(L, 0);
-    for (auto& L : L_am) ok &= finish(L, 0);
-    for (auto& L : L_seed) ok &= finish(L, 0);
+    for (auto& L : L_est) ok &= finish(5, L, 0);
+    for (auto& L : L_am) ok &= finish(6, L, 0);
+    for (auto& L : L_seed) ok &= finish(7, L, 0);
     for (auto& R : L_lvl)
-        for (auto& L : R) ok &= finish(L, full_level);
+        for (auto& L : R) ok &= finish(8, L, full_level);
     for (auto& R : L_cmp)
-        for (auto& L : R) ok &= finish(L, 0);
-    for (auto& L : L_fin) ok &= finish(L, 0);
+        for (auto& L : R) ok &= finish(9, L, 0);
+    for (auto& L : L_fin) ok &= finish(10, L, 0);
     if (!ok) return set_error(IM_EINVAL, "too many queries for one tick's argument buffer");
-    IMX_HIP(hipMemcpyAsync(args_dev_, args_host_, args_off_, hipMemcpyHostToDevice, st_));
 
-    // ---- launches, in dependency order
+    // ---- the tick's work, in dependency order: argument records in, kernels,
+    // status records out.  `timed` adds the HIP events of the per-phase and
+    // per-launch times (not recorded in graph mode).
     const bool stats = profiling_level() >= 2;
     const bool sweeping = !rounds.empty(), cascading = !L_lvl.empty();
-    if (sweeping) IMX_HIP(hipEventRecord(ph_[0], st_));
-    for (auto& L : L_fill) IMX_HIP(launch_fill(L.dev, L.B, st_));
     int ne = 0;
-    for (auto& R : rounds) {
-        for (auto& L : R.prep) IMX_HIP(launch_sweep_prep(L.dev, L.B, st_));
-        IMX_HIP(hipEventRecord(ev_[2 * ne], st_));
-        for (auto& L : R.prop_first) IMX_HIP(launch_propagate(L.dev, L.B, L.maxJ, gs_first_, stats, st_));
-        for (auto& L : R.prop_rest) IMX_HIP(launch_propagate(L.dev, L.B, L.maxJ, gs_rest_, stats, st_));
-        IMX_HIP(hipEventRecord(ev_[2 * ne + 1], st_));
-        ++ne;
-        for (auto& L : R.mark) IMX_HIP(launch_mark(L.dev, L.B, st_));
+    auto issue = [&](bool timed, hipStream_t sx) -> hipError_t {
+        hipError_t e = hipMemcpyAsync(args_dev_, args_host_, args_off_, hipMemcpyHostToDevice, sx);
+        auto ev = [&](hipEvent_t x) {
+            if (timed && e == hipSuccess) e = hipEventRecord(x, sx);
+        };
+        if (sweeping) ev(ph_[0]);
+        for (auto& L : L_fill)
+            if (e == hipSuccess) e = launch_fill(L.dev, L.B, sx);
+        for (auto& R : rounds) {
+            for (auto& L : R.prep)
+                if (e == hipSuccess) e = launch_sweep_prep(L.dev, L.B, sx);
+            ev(ev_[2 * ne]);
+            for (auto& L : R.prop_first)
+                if (e == hipSuccess) e = launch_propagate(L.dev, L.B, L.maxJ, gs_first_, stats, sx);
+            for (auto& L : R.prop_rest)
+                if (e == hipSuccess) e = launch_propagate(L.dev, L.B, L.maxJ, gs_rest_, stats, sx);
+            ev(ev_[2 * ne + 1]);
+            ++ne;
+            for (auto& L : R.mark)
+                if (e == hipSuccess) e = launch_mark(L.dev, L.B, sx);
+        }
+        if (sweeping) ev(ph_[1]);
+        for (auto& L : L_est)
+            if (e == hipSuccess) e = launch_estimate(L.dev, L.B, sx);
+        if (cascading) ev(ph_[2]);
+        for (size_t i = 0; i < L_am.size(); ++i) {
+            Batch fin{};
+            fin.nq = L_am[i].B.nq;
+            for (int j = 0; j <= fin.nq; ++j) fin.wg0[j] = j;
+            if (e == hipSuccess) e = launch_argmax(L_am[i].dev, L_am[i].B, fin, sx);
+            if (e == hipSuccess) e = launch_cascade_seed(L_seed[i].dev, L_seed[i].B, sx);
+        }
+        for (size_t b = 0; b < L_lvl.size(); ++b) {
+            for (auto& L : L_lvl[b])
+                if (e == hipSuccess) e = launch_cascade_level(L.dev, L.B, L.maxJ, sx);
+            for (auto& L : L_cmp[b])
+                if (e == hipSuccess) e = launch_cascade_compact(L.dev, L.B, sx);
+        }
+        for (auto& L : L_fin)
+            if (e == hipSuccess) e = launch_cascade_finalize(L.dev, L.B, sx);
+        if (cascading) ev(ph_[3]);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(status_host_, status_dev_, sizeof(SlotStatus) * cap_, hipMemcpyDeviceToHost, sx);
+        return e;
+    };
+
+    const bool graph_mode = tune_.use_graphs != 0 && !stats;
+    hipStream_t cs = st_;  // stream of this tick's work
+    if (graph_mode) {
+        key.push_back((int64_t)args_off_);
+        key.push_back(gs_first_);
+        key.push_back(gs_rest_);
+        // the legacy null stream cannot be captured: use a private blocking
+        // stream then (implicitly ordered with the null stream)
+        if (!st_ && !gstream_) IMX_HIP(hipStreamCreate(&gstream_));
+        cs = st_ ? st_ : gstream_;
+        if (!graph_exec_ || key != graph_key_) {  // capture this structure once
+            drop_graph();
+            IMX_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            const hipError_t e = issue(false, cs);
+            hipGraph_t g = nullptr;
+            const hipError_t e2 = hipStreamEndCapture(cs, &g);
+            if (e != hipSuccess || e2 != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return set_error(IM_EDEVICE, std::string("graph capture: ") +
+                                                 hipGetErrorString(e != hipSuccess ? e : e2));
+            }
+            graph_ = g;
+            IMX_HIP(hipGraphInstantiate(&graph_exec_, graph_, nullptr, nullptr, 0));
+            graph_key_ = key;
+            ++graphs_built_;
+        }
+        IMX_HIP(hipGraphLaunch(graph_exec_, cs));
+        ++graph_replays_;
+    } else {
+        IMX_HIP(issue(true, st_));
     }
-    if (sweeping) IMX_HIP(hipEventRecord(ph_[1], st_));
-    for (auto& L : L_est) IMX_HIP(launch_estimate(L.dev, L.B, st_));
-    if (cascading) IMX_HIP(hipEventRecord(ph_[2], st_));
-    for (size_t i = 0; i < L_am.size(); ++i) {
-        Batch fin{};
-        fin.nq = L_am[i].B.nq;
-        for (int j = 0; j <= fin.nq; ++j) fin.wg0[j] = j;
-        IMX_HIP(launch_argmax(L_am[i].dev, L_am[i].B, fin, st_));
-        IMX_HIP(launch_cascade_seed(L_seed[i].dev, L_seed[i].B, st_));
-    }
-    for (size_t b = 0; b < L_lvl.size(); ++b) {
-        for (auto& L : L_lvl[b]) IMX_HIP(launch_cascade_level(L.dev, L.B, L.maxJ, st_));
-        for (auto& L : L_cmp[b]) IMX_HIP(launch_cascade_compact(L.dev, L.B, st_));
-    }
-    for (auto& L : L_fin) IMX_HIP(launch_cascade_finalize(L.dev, L.B, st_));
-    if (cascading) IMX_HIP(hipEventRecord(ph_[3], st_));
-    IMX_HIP(hipMemcpyAsync(status_host_, status_dev_, sizeof(SlotStatus) * cap_, hipMemcpyDeviceToHost, st_));
-    IMX_HIP(hipStreamSynchronize(st_));
+    IMX_HIP(hipStreamSynchronize(cs));
 
     float sweep_phase_ms = 0.f, cascade_phase_ms = 0.f;
-    if (sweeping) (void)hipEventElapsedTime(&sweep_phase_ms, ph_[0], ph_[1]);
-    if (cascading) (void)hipEventElapsedTime(&cascade_phase_ms, ph_[2], ph_[3]);
+    if (!graph_mode && sweeping) (void)hipEventElapsedTime(&sweep_phase_ms, ph_[0], ph_[1]);
+    if (!graph_mode && cascading) (void)hipEventElapsedTime(&cascade_phase_ms, ph_[2], ph_[3]);
     float prop_ms = 0.f;
-    for (int i = 0; i < ne; ++i) {
+    for (int i = 0; i < (graph_mode ? 0 : ne); ++i) {
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, ev_[2 * i], ev_[2 * i + 1]);
         prop_ms += ms;
@@ -911,6 +995,13 @@ im_status im_engine_get_tuning(const im_engine* e, im_tuning* t)
 {
     if (!e || !t) return imx::set_error(IM_EINVAL, "NULL argument");
     *t = e->eng->tuning();
+    return IM_OK;
+}
+
+im_status im_engine_counters(const im_engine* e, int64_t* steps, int64_t* graphs_built, int64_t* graph_replays)
+{
+    if (!e) return imx::set_error(IM_EINVAL, "engine is NULL");
+    e->eng->counters(steps, graphs_built, graph_replays);
     return IM_OK;
 }
 

@@ -166,3 +166,36 @@ def test_autotune_keeps_outputs(imx):
              dict(group_first=32, group_rest=64, rounds_per_step=4, dense_div=8)]
     out = autotune.autotune(qs, candidates=cands)
     assert out["best"] in cands and len(out["table"]) == 2
+
+
+def test_engine_graph_mode_equals_solo(imx):
+    """Steps captured in HIP graphs and replayed give the same results as
+    direct launches, including when queries join and leave (new structures)."""
+    cases = _graphs()
+    Gs = [imx.Graph.from_graphgen(g) for g, *_ in cases]
+    solo = [_solo(imx, G, J, s, K) for G, (_, J, s, K) in zip(Gs, cases)]
+    E = imx.Engine(max_queries=16)
+    E.set_tuning(use_graphs=1, rounds_per_step=4)
+    ids = [E.submit(G, J, s, K) for G, (_, J, s, K) in zip(Gs, cases)]
+    res = E.run()
+    for qid, r in zip(ids, solo):
+        _same(res[qid], r)
+    c = E.counters()
+    _say(f"[graphs] {c}")
+    assert c["graphs_built"] >= 1 and c["graph_replays"] > c["graphs_built"]
+    # continuous admission in graph mode
+    pending = list(range(len(cases)))
+    got, idmap, steps = {}, {}, 0
+    while pending or E.info()["queries"]:
+        if pending and steps % 2 == 0:
+            i = pending.pop(0)
+            G, (_, J, s, K) = Gs[i], cases[i]
+            idmap[E.submit(G, J, s, K)] = i
+        E.step()
+        steps += 1
+        for qid in E.poll():
+            got[idmap[qid]] = E.result(qid)
+        assert steps < 100000
+    for i, r in enumerate(solo):
+        _same(got[i], r)
+    E.free()
