@@ -210,7 +210,7 @@ def batched_main(args):
     # autotune on every 8th query (not timed)
     tuned = autotune.autotune(queries[::8], candidates=[
         dict(group_first=gf, group_rest=gr, rounds_per_step=r, dense_div=16)
-        for gf in (32, 64) for gr in (16, 32, 64) for r in (4, 8, 16)], stream=stream)
+        for gf in (0, 64) for gr in (0, 32, 64) for r in (4, 8, 16)], stream=stream)
     tuning = tuned["best"]
     print(f"[bench] tuning {tuning}", file=sys.stderr, flush=True)
 

@@ -218,7 +218,9 @@ im_status im_engine_create(int32_t max_queries, uint64_t hbm_budget_bytes, void*
 
 /* Scheduling parameters of an engine (they change speed, never results):
  *   group_first, group_rest  lanes per propagation task (16, 32 or 64) in the
- *                            first sweep after a fill and in later sweeps;
+ *                            first sweep after a fill and in later sweeps, or
+ *                            0 for the packed kernel (each wave takes
+ *                            max(1, min(16, 2048 / J)) tasks at once);
  *   rounds_per_step          sweeps / cascade levels launched per step (1..16);
  *   dense_div                a sweep visits every task instead of an active
  *                            list when more than n / dense_div rows changed in
@@ -228,7 +230,7 @@ im_status im_engine_create(int32_t max_queries, uint64_t hbm_budget_bytes, void*
  *                            query split) occurs and replayed while it repeats
  *                            (no per-launch kernel times then); 0: direct
  *                            launches.
- * Defaults: 64, 64, 8, 16, 0; the environment variables IMX_GROUP_FIRST,
+ * Defaults: 0, 0, 8, 16, 0; the environment variables IMX_GROUP_FIRST,
  * IMX_GROUP, IMX_ROUNDS, IMX_DENSE_DIV and IMX_GRAPHS override them at engine
  * creation (an out-of-range value makes creation fail with IM_EINVAL). */
 typedef struct im_tuning {

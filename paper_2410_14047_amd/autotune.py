@@ -15,11 +15,12 @@ from typing import Iterable, Optional
 
 from .binding import Engine, Graph
 
-DEFAULT = dict(group_first=64, group_rest=64, rounds_per_step=8, dense_div=16, use_graphs=0)
+DEFAULT = dict(group_first=0, group_rest=0, rounds_per_step=8, dense_div=16, use_graphs=0)
 
 
 def candidate_grid(J_max: int) -> list:
-    gs = [g for g in (16, 32, 64) if g >= (16 if J_max <= 1024 else 32 if J_max <= 2048 else 64)]
+    # 0 = packed propagation (several tasks per wave); else lanes per task
+    gs = [0] + [g for g in (16, 32, 64) if g >= (16 if J_max <= 1024 else 32 if J_max <= 2048 else 64)]
     out = []
     for gf, gr, r, d in itertools.product(gs, gs, (4, 8, 16), (8, 16, 64)):
         out.append(dict(group_first=gf, group_rest=gr, rounds_per_step=r, dense_div=d))

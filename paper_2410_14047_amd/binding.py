@@ -388,7 +388,7 @@ class Engine:
         del self._K[qid]
         return dict(seeds=seeds, spread=spread.value, est=est, T=T, stats=stats.as_dict())
 
-    def set_tuning(self, group_first: int = 64, group_rest: int = 64, rounds_per_step: int = 8,
+    def set_tuning(self, group_first: int = 0, group_rest: int = 0, rounds_per_step: int = 8,
                    dense_div: int = 16, use_graphs: int = 0) -> None:
         t = im_tuning(group_first, group_rest, rounds_per_step, dense_div, int(use_graphs))
         _check(lib().im_engine_set_tuning(self.handle, ctypes.byref(t)))

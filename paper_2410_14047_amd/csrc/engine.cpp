@@ -328,7 +328,7 @@ public:
 
     im_status set_tuning(const im_tuning& t)
     {
-        auto ok_gs = [](int v) { return v == 16 || v == 32 || v == 64; };
+        auto ok_gs = [](int v) { return v == 0 || v == 16 || v == 32 || v == 64; };
         if (!ok_gs(t.group_first) || !ok_gs(t.group_rest) || t.rounds_per_step < 1 ||
             t.rounds_per_step > kMaxRounds || t.dense_div < 1 || (t.use_graphs != 0 && t.use_graphs != 1))
             return set_error(IM_EINVAL, "tuning out of range");
@@ -411,7 +411,7 @@ private:
         graph_ = nullptr;
         graph_key_.clear();
     }
-    im_tuning tune_{64, 64, 8, 16, 0};
+    im_tuning tune_{0, 0, 8, 16, 0};
 };
 
 im_status Engine::step()

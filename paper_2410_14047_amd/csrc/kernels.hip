@@ -947,6 +947,330 @@ __global__ __launch_bounds__(kWG, 6) void k_propagate(const PropArgs* __restrict
     }
 }
 
+// ---------------------------------------------------------------------------
+// Packed variant of the propagation: each wave takes a pack of P consecutive
+// entries of the task list (P = 2048 / J rows, at least 1, at most 16) and
+// stages all P rows of u in LDS; the pack's arcs are flattened over the 64
+// lanes, so the fixed costs of a task (record and row loads, scans, the store
+// and the flagging) are paid once per pack and lanes stay busy on small
+// tasks.  Every merge is the same byte-wise max as in k_propagate; results
+// are identical (the fixed point does not depend on the schedule).
+
+constexpr int kPackBytes = 2048;  // register bytes of the rows one wave stages per pack
+__host__ __device__ inline int pack_rows(int J)
+{
+    const int p = kPackBytes / J;
+    return p < 1 ? 1 : (p > 16 ? 16 : p);
+}
+
+constexpr int kPackMax = 16;
+// LDS words per wave of the packed kernel besides the rows: dirty bits,
+// per-arc arrays (ev, eh, eW, edl, est, ek: 6 x 64), task records (u, e0 lo/hi,
+// prefix, split, touched, active, changed, in_first, in_cnt: 10 x 16 + 1),
+// sector masks (2 x 64, instrumented variant), list buffer.
+constexpr int kPackArcWords = 6 * 64;
+constexpr int kPackTaskWords = 10 * kPackMax + 16;
+__host__ __device__ inline int pack_row_words(int maxJ) { return (maxJ / 4 > kPackBytes / 4) ? maxJ / 4 : kPackBytes / 4; }
+__host__ __device__ inline int pack_dirty_words(int maxJ) { return pack_row_words(maxJ) / 32; }
+__host__ __device__ inline int pack_wave_words(int maxJ)
+{
+    return pack_row_words(maxJ) + pack_dirty_words(maxJ) + kPackArcWords + kPackTaskWords + 2 * 64 + kPropBufCap;
+}
+
+template <bool STATS>
+__global__ __launch_bounds__(kWG, 6) void k_propagate_pack(const PropArgs* __restrict__ args, Batch B, int maxJ)
+{
+    IMX_BATCH_PROLOGUE(PropArgs);
+    extern __shared__ uint32_t smem[];
+    const int J = a.J;
+    const int Jw = J >> 2;
+    const int P = pack_rows(J);
+    const int wave = (int)(threadIdx.x >> 6);
+    const int lane = lane_id();
+
+    const GraphDev& g = a.g;
+    const bool sweep0 = a.tasks == nullptr;
+    const bool all = sweep0 || *a.dense != 0u;
+    const int32_t* tasks = all ? nullptr : a.tasks;
+    const int64_t count = all ? g.ntasks : (int64_t)*a.task_count;
+    const int64_t npacks = (count + P - 1) / P;
+    if (*a.conv != ~0u) return;                // the build has converged
+    if (lb * kWaves >= npacks) return;          // no pack for this workgroup (uniform)
+
+    uint32_t* sX = smem;
+    const uint32_t* sT = smem + J;
+    const int XT = ((maxJ + kTableWords) + 3) & ~3;
+    uint32_t* wbase = smem + XT + wave * pack_wave_words(maxJ);
+    uint32_t* rows = wbase;                                      // P x Jw words
+    uint32_t* dirty = rows + pack_row_words(maxJ);               // P x Jw bits
+    int* ev = reinterpret_cast<int*>(dirty + pack_dirty_words(maxJ));
+    uint32_t* eh = reinterpret_cast<uint32_t*>(ev + 64);
+    uint32_t* eW = eh + 64;
+    int* edl = reinterpret_cast<int*>(eW + 64);
+    int* est = edl + 64;
+    int* ek = est + 64;
+    int* T_u = ek + 64;
+    uint32_t* T_e0lo = reinterpret_cast<uint32_t*>(T_u + kPackMax);
+    uint32_t* T_e0hi = T_e0lo + kPackMax;
+    int* T_pre = reinterpret_cast<int*>(T_e0hi + kPackMax);  // kPackMax + 1
+    int* T_split = T_pre + kPackMax + 1;
+    int* T_touch = T_split + kPackMax;
+    int* T_act = T_touch + kPackMax;
+    int* T_chg = T_act + kPackMax;
+    int* T_in0 = T_chg + kPackMax;
+    int* T_inc = T_in0 + kPackMax;
+    unsigned long long* esec =
+        reinterpret_cast<unsigned long long*>(wbase + pack_row_words(maxJ) + pack_dirty_words(maxJ) + kPackArcWords +
+                                              kPackTaskWords);  // STATS only; 8-byte aligned (all counts even)
+    int32_t* wbuf = reinterpret_cast<int32_t*>(esec + 64);
+    WaveList chl{wbuf, 0, a.chg_list, a.chg_count, kPropBufCap};
+    unsigned long long c_tasks = 0, c_rows = 0, c_wbytes = 0, c_scanned = 0, c_active = 0, c_sectors = 0;
+    unsigned long long c_changed = 0, c_visited = 0;
+
+    for (int i = threadIdx.x; i < J + kBuckets + 1; i += kWG) sX[i] = a.X[i];
+    __syncthreads();
+
+    const uint32_t* M32 = reinterpret_cast<const uint32_t*>(a.M);
+    uint32_t* MW = reinterpret_cast<uint32_t*>(a.M);
+    const uint4* M4 = reinterpret_cast<const uint4*>(a.M);
+    const uint32_t* chg_prev = a.chg_prev;
+    const int chunks16 = J / 16;  // 16-byte chunks per row
+    const int dwords = (P * Jw + 31) / 32;
+
+    // Task records are loaded one pack ahead and task ids two packs ahead
+    // (lanes 0..P-1 hold the pack's tasks).
+    const int64_t pstride = lg * kWaves;
+    auto task_id = [&](int64_t pk) -> int32_t {
+        const int64_t q = pk * P + lane;
+        return (lane < P && pk < npacks && q < count) ? (tasks ? tasks[q] : (int32_t)q) : -1;
+    };
+    int64_t pk = lb * kWaves + wave;
+    int32_t t_nx = task_id(pk);
+    int32_t u_nx = 0;
+    int64_t e0_nx = 0;
+    uint32_t len_nx = 0;
+    if (t_nx >= 0) {
+        u_nx = g.task_u[t_nx];
+        e0_nx = g.task_e0[t_nx];
+        len_nx = g.task_len[t_nx];
+    }
+    int32_t t_nx2 = task_id(pk + pstride);
+    for (; pk < npacks; pk += pstride) {
+        const int32_t t = t_nx, u = u_nx;
+        const int64_t e0 = e0_nx;
+        const uint32_t len = len_nx;
+        int in0 = 0, inc = 0;
+        if (t >= 0) {
+            in0 = g.in_task_start[u];
+            inc = g.in_task_start[u + 1] - in0;
+        }
+        // next pack's records, and the ids of the one after
+        t_nx = t_nx2;
+        if (t_nx >= 0) {
+            u_nx = g.task_u[t_nx];
+            e0_nx = g.task_e0[t_nx];
+            len_nx = g.task_len[t_nx];
+        }
+        t_nx2 = task_id(pk + 2 * pstride);
+        const int na = (t >= 0) ? (int)(len & 0x7fffffffu) : 0;
+        const int incl = wave_incl_scan(na);
+        const int A = __shfl(incl, 63, 64);
+        if (lane < P) {
+            T_u[lane] = (t >= 0) ? u : -1;
+            T_e0lo[lane] = (uint32_t)e0;
+            T_e0hi[lane] = (uint32_t)((uint64_t)e0 >> 32);
+            T_pre[lane] = incl - na;
+            T_split[lane] = (len >> 31) ? 1 : 0;
+            T_touch[lane] = 0;
+            T_act[lane] = 0;
+            T_chg[lane] = 0;
+            T_in0[lane] = in0;
+            T_inc[lane] = inc;
+        }
+        if (lane == 0) T_pre[P] = A;
+        if (STATS && t >= 0) ++c_tasks;
+        wave_lds_sync();
+        // stage the P rows (16-byte chunks) and clear the dirty bits
+        for (int c = lane; c < P * chunks16; c += 64) {
+            const int k = c / chunks16, w = c - k * chunks16;
+            const int uk = T_u[k];
+            const uint4 d = (uk >= 0) ? M4[(size_t)uk * (size_t)chunks16 + w] : make_uint4(0u, 0u, 0u, 0u);
+            reinterpret_cast<uint4*>(rows)[c] = d;
+        }
+        for (int i = lane; i < dwords; i += 64) dirty[i] = 0u;
+        wave_lds_sync();
+
+        for (int base = 0; base < A; base += 64) {
+            const int ai = base + lane;
+            int k = 0, cnt = 0, lo = 0, hi = 0;
+            int32_t v = 0;
+            uint32_t h = 0, w = 0;
+            bool act_arc = false;
+            if (ai < A) {
+#pragma unroll
+                for (int step = kPackMax / 2; step > 0; step >>= 1)
+                    if (k + step < P && T_pre[k + step] <= ai) k += step;
+                const int64_t e = (int64_t)(((uint64_t)T_e0hi[k] << 32) | T_e0lo[k]) + (ai - T_pre[k]);
+                v = g.col[e];
+                w = g.W[e];
+                act_arc = sweep0 || ((chg_prev[(uint32_t)v >> 5] >> (v & 31)) & 1u);
+                if (act_arc && w != 0u) {
+                    h = arc_hash((uint32_t)T_u[k], (uint32_t)v);
+                    candidate_range(sX, sT, J, h, w, lo, hi);
+                    cnt = hi - lo;
+                }
+                if (STATS && act_arc) T_act[k] = 1;
+                if (cnt > 0) T_touch[k] = 1;
+            }
+            if (STATS) {
+                c_scanned += (ai < A) ? 1ull : 0ull;
+                c_active += act_arc ? 1ull : 0ull;
+            }
+            const bool dense = cnt > 0 && 2 * cnt >= J;
+            const int nd = (cnt > 0 && !dense) ? (((hi - 1) >> 2) - (lo >> 2) + 1) : 0;
+
+            // dense arcs: the wave merges v's row word by word into row k
+            unsigned long long rem = __ballot(dense);
+            while (rem) {
+                const int ak = __ffsll((long long)rem) - 1;
+                rem &= rem - 1ull;
+                const int vk = __shfl(v, ak, 64), kk = __shfl(k, ak, 64);
+                const uint32_t hk = __shfl(h, ak, 64), wk = __shfl(w, ak, 64);
+                const int lok = __shfl(lo, ak, 64), hik = __shfl(hi, ak, 64);
+                const uint32_t* src = M32 + (size_t)vk * (size_t)Jw;
+                uint32_t* rk = rows + kk * Jw;
+                for (int idx = lane; idx < Jw; idx += 64) {
+                    if (4 * idx + 3 >= lok && 4 * idx < hik) {
+                        const uint32_t val = src[idx] & live_mask4(*reinterpret_cast<const uint4*>(&sX[4 * idx]), hk, wk);
+                        const uint32_t cur = rk[idx];
+                        const uint32_t want = bytemax4(cur, val);
+                        if (want != cur) {
+                            rk[idx] = want;
+                            const int bit = kk * Jw + idx;
+                            atomicOr(&dirty[bit >> 5], 1u << (bit & 31));
+                        }
+                    }
+                }
+                if (STATS && lane == 0) c_sectors += (unsigned long long)(((hik - 1) >> 6) - (lok >> 6) + 1);
+            }
+
+            // sparse arcs: flattened (arc, word) items over the wave
+            const int iincl = wave_incl_scan(nd);
+            const int total = __shfl(iincl, 63, 64);
+            if (total == 0) continue;
+            ev[lane] = v;
+            eh[lane] = h;
+            eW[lane] = w;
+            edl[lane] = lo >> 2;
+            est[lane] = iincl - nd;
+            ek[lane] = k * Jw;
+            if (STATS) esec[lane] = 0ull;
+            wave_lds_sync();
+            for (int r = 0; r < total; r += 2 * 64) {
+                uint32_t val0 = 0u, val1 = 0u;
+                int d0 = 0, d1 = 0;
+                const int i0 = r + lane, i1 = r + 64 + lane;
+                if (i0 < total) {
+                    const int o = owner_of(est, i0);
+                    const int dw = edl[o] + (i0 - est[o]);
+                    d0 = ek[o] + dw;
+                    const uint32_t m = live_mask4(*reinterpret_cast<const uint4*>(&sX[4 * dw]), eh[o], eW[o]);
+                    if (m) {
+                        val0 = M32[(size_t)ev[o] * (size_t)Jw + (size_t)dw] & m;
+                        if (STATS) atomicOr(&esec[o], 1ull << ((4 * dw) >> 6));
+                    }
+                }
+                if (i1 < total) {
+                    const int o = owner_of(est, i1);
+                    const int dw = edl[o] + (i1 - est[o]);
+                    d1 = ek[o] + dw;
+                    const uint32_t m = live_mask4(*reinterpret_cast<const uint4*>(&sX[4 * dw]), eh[o], eW[o]);
+                    if (m) {
+                        val1 = M32[(size_t)ev[o] * (size_t)Jw + (size_t)dw] & m;
+                        if (STATS) atomicOr(&esec[o], 1ull << ((4 * dw) >> 6));
+                    }
+                }
+                lds_merge_word(&rows[d0], dirty, d0, val0, val0 != 0u);
+                lds_merge_word(&rows[d1], dirty, d1, val1, val1 != 0u);
+            }
+            if (STATS) c_sectors += (unsigned long long)__popcll(esec[lane]);
+            wave_lds_sync();
+        }
+        wave_lds_sync();
+
+        // store changed words of every row of the pack
+        for (int idx = lane; idx < P * Jw; idx += 64) {
+            if (!((dirty[idx >> 5] >> (idx & 31)) & 1u)) continue;
+            const int k = idx / Jw, d = idx - k * Jw;
+            const uint32_t nwd = rows[idx];
+            uint32_t* dst = MW + (size_t)T_u[k] * (size_t)Jw + d;
+            if (!T_split[k]) {
+                *dst = nwd;
+                T_chg[k] = 1;
+                if (STATS) c_wbytes += 4;
+            } else {
+                uint32_t cur = *dst;
+                for (;;) {
+                    const uint32_t want = bytemax4(cur, nwd);
+                    if (want == cur) break;
+                    const uint32_t prev = atomicCAS(dst, cur, want);
+                    if (prev == cur) {
+                        T_chg[k] = 1;
+                        if (STATS) c_wbytes += 4;
+                        break;
+                    }
+                    cur = prev;
+                }
+            }
+        }
+        wave_lds_sync();
+        // flag changed rows once per sweep; the first flagger queues u's in-tasks
+        bool first = false;
+        if (lane < P && T_u[lane] >= 0 && T_chg[lane]) {
+            const int uu = T_u[lane];
+            const uint32_t bit = 1u << (uu & 31);
+            if (!T_split[lane]) {
+                atomicOr(&a.chg_next[(uint32_t)uu >> 5], bit);
+                first = true;
+            } else {
+                first = !(atomicOr(&a.chg_next[(uint32_t)uu >> 5], bit) & bit);
+            }
+        }
+        if (first) ++c_changed;
+        if (STATS && lane < P && T_u[lane] >= 0) {
+            if (T_touch[lane]) ++c_rows;
+            if (T_act[lane] && atomicMax(&a.vstamp[T_u[lane]], a.stamp_id) < a.stamp_id) ++c_visited;
+        }
+        wl_append_ranges(chl, first ? T_inc[lane] : 0, lane < P ? T_in0[lane] : 0);
+        wave_lds_sync();
+    }
+    wl_flush(chl);
+    {
+        const unsigned long long tot = wave_sum_u64(c_changed);
+        if (lane == 0 && tot) atomicAdd(a.rows_changed, tot);
+    }
+    if (STATS) {
+        c_wbytes = wave_sum_u64(c_wbytes);
+        c_tasks = wave_sum_u64(c_tasks);
+        c_rows = wave_sum_u64(c_rows);
+        c_scanned = wave_sum_u64(c_scanned);
+        c_active = wave_sum_u64(c_active);
+        c_sectors = wave_sum_u64(c_sectors);
+        c_visited = wave_sum_u64(c_visited);
+        const unsigned long long chg_tot = wave_sum_u64(c_changed);
+        if (lane == 0) {
+            atomicAdd(&a.stats->rows_visited, c_visited);
+            atomicAdd(&a.stats->rows_changed, chg_tot);
+            atomicAdd(&a.stats->tasks, c_tasks);
+            atomicAdd(&a.stats->rows_read, c_rows);
+            atomicAdd(&a.stats->bytes_written, c_wbytes);
+            atomicAdd(&a.stats->arcs_scanned, c_scanned);
+            atomicAdd(&a.stats->arcs_active, c_active);
+            atomicAdd(&a.stats->sectors, c_sectors);
+        }
+    }
+}
+
 // Launch-configuration caches below are shared by every engine of the
 // process; engines may step on different host threads.
 static std::mutex g_launch_cfg_mutex;
@@ -1007,11 +1331,47 @@ static hipError_t launch_propagate_t(const PropArgs* args, const Batch& B, int m
 
 // Lane-group size for a row width: the smallest of 16/32/64 lanes that keeps
 // at most 16 words of the row per lane, unless a larger one is requested.
+// Lanes per task: the lane-group size (16, 32 or 64, at least what keeps 16
+// words of the row per lane), or for the packed kernel (requested 0) the
+// wave's 64 lanes shared by pack_rows(J) tasks.
 int propagate_group_size(int J, int requested)
 {
+    if (requested == 0) {
+        const int l = 64 / pack_rows(J);
+        return l < 1 ? 1 : l;
+    }
     int gs = (J <= 1024) ? 16 : (J <= 2048) ? 32 : 64;
     if (requested == 16 || requested == 32 || requested == 64) gs = requested > gs ? requested : gs;
     return gs;
+}
+
+static size_t pack_lds(int maxJ)
+{
+    const int XT = ((maxJ + kTableWords) + 3) & ~3;
+    return sizeof(uint32_t) * ((size_t)XT + (size_t)kWaves * (size_t)pack_wave_words(maxJ));
+}
+
+template <bool STATS>
+static hipError_t pack_setup(int maxJ, int* per_cu)
+{
+    const size_t lds = pack_lds(maxJ);
+    std::lock_guard<std::mutex> lock(g_launch_cfg_mutex);
+    static size_t lds_set = 0, attr_set = 0;
+    static int cached = 0;
+    if (lds_set != lds) {
+        if (lds > attr_set) {
+            hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_propagate_pack<STATS>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (err != hipSuccess) return err;
+            attr_set = lds;
+        }
+        hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&cached, k_propagate_pack<STATS>, kWG, lds);
+        if (err != hipSuccess) return err;
+        if (cached < 1) cached = 1;
+        lds_set = lds;
+    }
+    *per_cu = cached;
+    return hipSuccess;
 }
 
 // Calls f.template operator()<GS, DPLG, STATS>() for the configuration of
@@ -1032,6 +1392,12 @@ static hipError_t propagate_dispatch(int maxJ, int gs, bool stats, F&& f)
 
 hipError_t propagate_full_grid(int maxJ, int gs, bool stats, int* grid)
 {
+    if (gs == 0) {
+        int per_cu = 0;
+        const hipError_t e = stats ? pack_setup<true>(maxJ, &per_cu) : pack_setup<false>(maxJ, &per_cu);
+        *grid = cu_count() * per_cu;
+        return e;
+    }
     return propagate_dispatch(maxJ, gs, stats, [&]<int G, int D, bool S>() -> hipError_t {
         int per_cu = 0;
         hipError_t e = propagate_setup<G, D, S>(maxJ, &per_cu);
@@ -1044,6 +1410,17 @@ int propagate_lanes_per_task(int maxJ, int gs) { return propagate_group_size(max
 
 hipError_t launch_propagate(const PropArgs* args, const Batch& B, int maxJ, int gs, bool stats, hipStream_t st)
 {
+    if (gs == 0) {
+        int per_cu = 0;
+        hipError_t e = stats ? pack_setup<true>(maxJ, &per_cu) : pack_setup<false>(maxJ, &per_cu);
+        if (e != hipSuccess) return e;
+        const size_t lds = pack_lds(maxJ);
+        if (stats)
+            hipLaunchKernelGGL(k_propagate_pack<true>, dim3(B.wg0[B.nq]), dim3(kWG), lds, st, args, B, maxJ);
+        else
+            hipLaunchKernelGGL(k_propagate_pack<false>, dim3(B.wg0[B.nq]), dim3(kWG), lds, st, args, B, maxJ);
+        return hipGetLastError();
+    }
     return propagate_dispatch(maxJ, gs, stats, [&]<int G, int D, bool S>() -> hipError_t {
         return launch_propagate_t<G, D, S>(args, B, maxJ, st);
     });

@@ -91,6 +91,25 @@ def test_parity_with_oracle(imx, orc, name):
     assert_parity(orc, gpu, ref, J, seed)
 
 
+# The lane-group propagation kernels (16/32/64 lanes per task), selected
+# through the environment at sketch creation; the default is the packed kernel.
+LANE_GROUP_CASES = ["er300_tri_J192", "er200_p0.01_J1024", "er150_p0.3_J4096", "hub2000_p0.2_J256",
+                    "rmat12_wc_J512"]
+
+
+@pytest.mark.parametrize("groups", [("64", "64"), ("16", "32"), ("32", "16")])
+@pytest.mark.parametrize("name", LANE_GROUP_CASES)
+def test_lane_group_kernels_with_oracle(imx, orc, monkeypatch, name, groups):
+    make, J, seed, K = CASES[name]
+    g = make()
+    monkeypatch.setenv("IMX_GROUP_FIRST", groups[0])
+    monkeypatch.setenv("IMX_GROUP", groups[1])
+    _say(f"[lane groups {groups}] {name}")
+    ref = orc.greedy(g, J, seed, K)
+    gpu = run_gpu(imx, g, J, seed, K)
+    assert_parity(orc, gpu, ref, J, seed)
+
+
 @pytest.mark.parametrize("n,K", [(1, 1), (10, 10)])
 def test_edgeless_graphs(imx, orc, n, K):
     g = graphgen.Graph(n=n, rowptr=np.zeros(n + 1, np.int64), col=np.zeros(0, np.int32),
