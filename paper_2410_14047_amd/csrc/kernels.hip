@@ -637,6 +637,25 @@ constexpr int kItemsPerLane = 2;
 
 // Six waves per SIMD: the kernel is bound by the latency of dependent
 // gathers, and this is the most waves that fit without register spills.
+// As lds_merge_word, with the changed word recorded as a dirty byte (plain
+// LDS byte stores: no atomics on shared dirty words).
+__device__ __forceinline__ void lds_merge_word8(uint32_t* w, uint8_t* dirty8, int d, uint32_t val, bool pending)
+{
+    while (__ballot(pending) != 0ull) {
+        if (pending) {
+            const uint32_t cur = *w;
+            const uint32_t want = bytemax4(cur, val);
+            if (want == cur) {
+                pending = false;
+            } else {
+                *w = want;
+                dirty8[d] = 1u;
+            }
+        }
+        wave_lds_sync();
+    }
+}
+
 template <int GS, int DPLG, bool STATS>
 __global__ __launch_bounds__(kWG, 6) void k_propagate(const PropArgs* __restrict__ args, Batch B)
 {
@@ -964,21 +983,24 @@ __host__ __device__ inline int pack_rows(int J)
 }
 
 constexpr int kPackMax = 16;
-// LDS words per wave of the packed kernel besides the rows: dirty bits,
+// LDS words per wave of the packed kernel besides the rows: dirty bytes,
 // per-arc arrays (ev, eh, eW, edl, est, ek: 6 x 64), task records (u, e0 lo/hi,
 // prefix, split, touched, active, changed, in_first, in_cnt: 10 x 16 + 1),
 // sector masks (2 x 64, instrumented variant), list buffer.
 constexpr int kPackArcWords = 6 * 64;
 constexpr int kPackTaskWords = 10 * kPackMax + 16;
 __host__ __device__ inline int pack_row_words(int maxJ) { return (maxJ / 4 > kPackBytes / 4) ? maxJ / 4 : kPackBytes / 4; }
-__host__ __device__ inline int pack_dirty_words(int maxJ) { return pack_row_words(maxJ) / 32; }
+__host__ __device__ inline int pack_dirty_words(int maxJ) { return pack_row_words(maxJ) / 4; }  // one byte per row word
+constexpr int kPackBufCap = 128;  // staging entries per wave for the changed in-task list
 __host__ __device__ inline int pack_wave_words(int maxJ)
 {
-    return pack_row_words(maxJ) + pack_dirty_words(maxJ) + kPackArcWords + kPackTaskWords + 2 * 64 + kPropBufCap;
+    return pack_row_words(maxJ) + pack_dirty_words(maxJ) + kPackArcWords + kPackTaskWords + 2 * 64 + kPackBufCap;
 }
 
+// Five waves per SIMD: the LDS of a workgroup (about 31 KB at J <= 2048)
+// admits five workgroups per CU, so registers may use that occupancy's share.
 template <bool STATS>
-__global__ __launch_bounds__(kWG, 6) void k_propagate_pack(const PropArgs* __restrict__ args, Batch B, int maxJ)
+__global__ __launch_bounds__(kWG, 5) void k_propagate_pack(const PropArgs* __restrict__ args, Batch B, int maxJ)
 {
     IMX_BATCH_PROLOGUE(PropArgs);
     extern __shared__ uint32_t smem[];
@@ -1002,8 +1024,8 @@ __global__ __launch_bounds__(kWG, 6) void k_propagate_pack(const PropArgs* __res
     const int XT = ((maxJ + kTableWords) + 3) & ~3;
     uint32_t* wbase = smem + XT + wave * pack_wave_words(maxJ);
     uint32_t* rows = wbase;                                      // P x Jw words
-    uint32_t* dirty = rows + pack_row_words(maxJ);               // P x Jw bits
-    int* ev = reinterpret_cast<int*>(dirty + pack_dirty_words(maxJ));
+    uint8_t* dirty8 = reinterpret_cast<uint8_t*>(rows + pack_row_words(maxJ));  // P x Jw bytes
+    int* ev = reinterpret_cast<int*>(rows + pack_row_words(maxJ) + pack_dirty_words(maxJ));
     uint32_t* eh = reinterpret_cast<uint32_t*>(ev + 64);
     uint32_t* eW = eh + 64;
     int* edl = reinterpret_cast<int*>(eW + 64);
@@ -1023,7 +1045,7 @@ __global__ __launch_bounds__(kWG, 6) void k_propagate_pack(const PropArgs* __res
         reinterpret_cast<unsigned long long*>(wbase + pack_row_words(maxJ) + pack_dirty_words(maxJ) + kPackArcWords +
                                               kPackTaskWords);  // STATS only; 8-byte aligned (all counts even)
     int32_t* wbuf = reinterpret_cast<int32_t*>(esec + 64);
-    WaveList chl{wbuf, 0, a.chg_list, a.chg_count, kPropBufCap};
+    WaveList chl{wbuf, 0, a.chg_list, a.chg_count, kPackBufCap};
     unsigned long long c_tasks = 0, c_rows = 0, c_wbytes = 0, c_scanned = 0, c_active = 0, c_sectors = 0;
     unsigned long long c_changed = 0, c_visited = 0;
 
@@ -1035,7 +1057,7 @@ __global__ __launch_bounds__(kWG, 6) void k_propagate_pack(const PropArgs* __res
     const uint4* M4 = reinterpret_cast<const uint4*>(a.M);
     const uint32_t* chg_prev = a.chg_prev;
     const int chunks16 = J / 16;  // 16-byte chunks per row
-    const int dwords = (P * Jw + 31) / 32;
+    const int dchunks = (P * Jw + 15) / 16;  // 16-byte chunks of the dirty bytes
 
     // Task records are loaded one pack ahead and task ids two packs ahead
     // (lanes 0..P-1 hold the pack's tasks).
@@ -1090,22 +1112,13 @@ __global__ __launch_bounds__(kWG, 6) void k_propagate_pack(const PropArgs* __res
         if (lane == 0) T_pre[P] = A;
         if (STATS && t >= 0) ++c_tasks;
         wave_lds_sync();
-        // stage the P rows (16-byte chunks) and clear the dirty bits
-        for (int c = lane; c < P * chunks16; c += 64) {
-            const int k = c / chunks16, w = c - k * chunks16;
-            const int uk = T_u[k];
-            const uint4 d = (uk >= 0) ? M4[(size_t)uk * (size_t)chunks16 + w] : make_uint4(0u, 0u, 0u, 0u);
-            reinterpret_cast<uint4*>(rows)[c] = d;
-        }
-        for (int i = lane; i < dwords; i += 64) dirty[i] = 0u;
-        wave_lds_sync();
-
-        for (int base = 0; base < A; base += 64) {
-            const int ai = base + lane;
-            int k = 0, cnt = 0, lo = 0, hi = 0;
-            int32_t v = 0;
-            uint32_t h = 0, w = 0;
-            bool act_arc = false;
+        // head id and threshold of arc ai of the pack (task k); the loads of
+        // the next chunk are issued while the current one is processed, and
+        // the first chunk's before the rows are staged
+        auto arc_load = [&](int ai, int& k, int32_t& v, uint32_t& w) {
+            k = 0;
+            v = 0;
+            w = 0;
             if (ai < A) {
 #pragma unroll
                 for (int step = kPackMax / 2; step > 0; step >>= 1)
@@ -1113,12 +1126,44 @@ __global__ __launch_bounds__(kWG, 6) void k_propagate_pack(const PropArgs* __res
                 const int64_t e = (int64_t)(((uint64_t)T_e0hi[k] << 32) | T_e0lo[k]) + (ai - T_pre[k]);
                 v = g.col[e];
                 w = g.W[e];
-                act_arc = sweep0 || ((chg_prev[(uint32_t)v >> 5] >> (v & 31)) & 1u);
-                if (act_arc && w != 0u) {
-                    h = arc_hash((uint32_t)T_u[k], (uint32_t)v);
-                    candidate_range(sX, sT, J, h, w, lo, hi);
-                    cnt = hi - lo;
-                }
+            }
+        };
+        int k_nx;
+        int32_t v_nx;
+        uint32_t w_nx;
+        arc_load(lane, k_nx, v_nx, w_nx);
+        // stage the P rows (16-byte chunks) and clear the dirty bits
+        for (int c = lane; c < P * chunks16; c += 64) {
+            const int k = c / chunks16, w = c - k * chunks16;
+            const int uk = T_u[k];
+            const uint4 d = (uk >= 0) ? M4[(size_t)uk * (size_t)chunks16 + w] : make_uint4(0u, 0u, 0u, 0u);
+            reinterpret_cast<uint4*>(rows)[c] = d;
+        }
+        // changed-head words of the first chunk (its arcs came with the rows)
+        uint32_t cw_nx = (lane < A && !sweep0) ? chg_prev[(uint32_t)v_nx >> 5] : ~0u;
+        for (int i = lane; i < dchunks; i += 64) reinterpret_cast<uint4*>(dirty8)[i] = make_uint4(0u, 0u, 0u, 0u);
+        wave_lds_sync();
+
+        for (int base = 0; base < A; base += 64) {
+            const int ai = base + lane;
+            const int k = k_nx;
+            const int32_t v = v_nx;
+            const uint32_t w = w_nx;
+            const uint32_t cw = cw_nx;
+            // the next chunk's arcs are loaded while this one is processed (and
+            // their changed-head words once the dense merges are issued); the
+            // hash and candidate range are computed while loads are in flight
+            if (base + 64 < A) arc_load(ai + 64, k_nx, v_nx, w_nx);
+            int cnt = 0, lo = 0, hi = 0;
+            uint32_t h = 0;
+            if (ai < A && w != 0u) {
+                h = arc_hash((uint32_t)T_u[k], (uint32_t)v);
+                candidate_range(sX, sT, J, h, w, lo, hi);
+            }
+            const bool act_arc = ai < A && ((cw >> (v & 31)) & 1u);
+            if (act_arc) cnt = hi - lo;
+            else lo = hi = 0;
+            if (ai < A) {
                 if (STATS && act_arc) T_act[k] = 1;
                 if (cnt > 0) T_touch[k] = 1;
             }
@@ -1146,13 +1191,14 @@ __global__ __launch_bounds__(kWG, 6) void k_propagate_pack(const PropArgs* __res
                         const uint32_t want = bytemax4(cur, val);
                         if (want != cur) {
                             rk[idx] = want;
-                            const int bit = kk * Jw + idx;
-                            atomicOr(&dirty[bit >> 5], 1u << (bit & 31));
+                            dirty8[kk * Jw + idx] = 1u;
                         }
                     }
                 }
                 if (STATS && lane == 0) c_sectors += (unsigned long long)(((hik - 1) >> 6) - (lok >> 6) + 1);
             }
+
+            if (base + 64 < A) cw_nx = (ai + 64 < A && !sweep0) ? chg_prev[(uint32_t)v_nx >> 5] : ~0u;
 
             // sparse arcs: flattened (arc, word) items over the wave
             const int iincl = wave_incl_scan(nd);
@@ -1190,8 +1236,8 @@ __global__ __launch_bounds__(kWG, 6) void k_propagate_pack(const PropArgs* __res
                         if (STATS) atomicOr(&esec[o], 1ull << ((4 * dw) >> 6));
                     }
                 }
-                lds_merge_word(&rows[d0], dirty, d0, val0, val0 != 0u);
-                lds_merge_word(&rows[d1], dirty, d1, val1, val1 != 0u);
+                lds_merge_word8(&rows[d0], dirty8, d0, val0, val0 != 0u);
+                lds_merge_word8(&rows[d1], dirty8, d1, val1, val1 != 0u);
             }
             if (STATS) c_sectors += (unsigned long long)__popcll(esec[lane]);
             wave_lds_sync();
@@ -1200,7 +1246,7 @@ __global__ __launch_bounds__(kWG, 6) void k_propagate_pack(const PropArgs* __res
 
         // store changed words of every row of the pack
         for (int idx = lane; idx < P * Jw; idx += 64) {
-            if (!((dirty[idx >> 5] >> (idx & 31)) & 1u)) continue;
+            if (!dirty8[idx]) continue;
             const int k = idx / Jw, d = idx - k * Jw;
             const uint32_t nwd = rows[idx];
             uint32_t* dst = MW + (size_t)T_u[k] * (size_t)Jw + d;
