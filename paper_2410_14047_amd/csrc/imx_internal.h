@@ -90,6 +90,15 @@ __host__ __device__ inline int row_lanes(int J)
 // Rows a lane group of the row-streaming kernels handles together (loads in flight).
 constexpr int kRowBatch = 4;
 
+// Packed propagation kernel: a wave takes pack_rows(J)
+// tasks at once, staging kPackBytes of register rows (at least one row).
+constexpr int kPackBytes = 2048;
+__host__ __device__ inline int pack_rows(int J)
+{
+    const int p = kPackBytes / J;
+    return p < 1 ? 1 : (p > 16 ? 16 : p);
+}
+
 // Per-vertex flag arrays are padded to whole 16-byte chunks.
 inline int64_t flag_bytes(int64_t n) { return (n + 15) / 16 * 16; }
 

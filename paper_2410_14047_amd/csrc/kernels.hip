@@ -975,12 +975,6 @@ __global__ __launch_bounds__(kWG, 6) void k_propagate(const PropArgs* __restrict
 // tasks.  Every merge is the same byte-wise max as in k_propagate; results
 // are identical (the fixed point does not depend on the schedule).
 
-constexpr int kPackBytes = 2048;  // register bytes of the rows one wave stages per pack
-__host__ __device__ inline int pack_rows(int J)
-{
-    const int p = kPackBytes / J;
-    return p < 1 ? 1 : (p > 16 ? 16 : p);
-}
 
 constexpr int kPackMax = 16;
 // LDS words per wave of the packed kernel besides the rows: dirty bytes,
@@ -1565,17 +1559,17 @@ __device__ __forceinline__ unsigned long long group_sum_u64(unsigned long long x
     return x;
 }
 
-// Ju and Hu terms of one 32-bit word of registers (covered registers are 0).
+// Ju and Hu terms of one 32-bit word of registers (covered registers are 0,
+// uncovered ones 1..33).  Without branches: every byte adds 2^(33 - r), a
+// covered one 2^33, and the caller subtracts 2^33 per covered register once
+// the uncovered count c is known (Hu = h - 2^33 * (registers - c)).
 __device__ __forceinline__ void est_word(uint32_t d, uint32_t& c, unsigned long long& h)
 {
+    // high bit of every nonzero byte
+    const uint32_t nz = (((d & 0x7f7f7f7fu) + 0x7f7f7f7fu) | d) & 0x80808080u;
+    c += (uint32_t)__builtin_popcount(nz);
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const uint32_t r = (d >> (8 * b)) & 0xffu;
-        if (r) {
-            ++c;
-            h += 1ull << (33u - r);
-        }
-    }
+    for (int b = 0; b < 4; ++b) h += 1ull << (33u - ((d >> (8 * b)) & 0xffu));
 }
 
 __global__ __launch_bounds__(kWG) void k_estimate(const EstArgs* __restrict__ args, Batch B)
@@ -1620,7 +1614,7 @@ __global__ __launch_bounds__(kWG) void k_estimate(const EstArgs* __restrict__ ar
             const unsigned long long hs = group_sum_u64(h[r], L);
             if (sub == 0 && v < a.n) {
                 a.Ju[v] = cs;
-                a.Hu[v] = hs;
+                a.Hu[v] = hs - ((unsigned long long)((uint32_t)a.J - cs) << 33);  // drop covered registers' 2^33
             }
         }
     }
