@@ -1840,12 +1840,24 @@ __global__ __launch_bounds__(kWG) void k_cascade_level(const LevelArgs* __restri
     const uint32_t* M32 = reinterpret_cast<const uint32_t*>(a.M);
     const int64_t nw = lg * kWaves;
 
-    for (int64_t i = lb * kWaves + wave; i < (int64_t)qn; i += nw) {
-        const int32_t t = Q[i];
+    // The next task's id is loaded one task ahead; the first chunk of arcs is
+    // loaded with u's row, and every later chunk while the previous one is
+    // processed.
+    int64_t i = lb * kWaves + wave;
+    int32_t t_next = (i < (int64_t)qn) ? Q[i] : 0;
+    for (; i < (int64_t)qn; i += nw) {
+        const int32_t t = t_next;
+        if (i + nw < (int64_t)qn) t_next = Q[i + nw];
         const int32_t u = g.task_u[t];
         const int64_t e0 = g.task_e0[t];
         const int64_t e1 = e0 + (int64_t)(g.task_len[t] & 0x7fffffffu);
         const uint32_t* Mu = M32 + (size_t)u * (size_t)Jw;
+        int32_t v_nx = 0;
+        uint32_t w_nx = 0;
+        if (e0 + lane < e1) {
+            v_nx = g.col[e0 + lane];
+            w_nx = g.W[e0 + lane];
+        }
         int nE = 0;
         for (int base = 0; base < Jw; base += 64) {
             const int idx = base + lane;
@@ -1864,11 +1876,18 @@ __global__ __launch_bounds__(kWG) void k_cascade_level(const LevelArgs* __restri
         for (int64_t cb = e0; cb < e1; cb += 64) {
             const int64_t e = cb + lane;
             int cnt = 0, pl = 0;
-            int32_t v = 0;
-            uint32_t h = 0, w = 0;
+            const int32_t v = v_nx;
+            const uint32_t w = w_nx;
+            uint32_t h = 0;
+            if (cb + 64 < e1) {
+                v_nx = 0;
+                w_nx = 0;
+                if (e + 64 < e1) {
+                    v_nx = g.col[e + 64];
+                    w_nx = g.W[e + 64];
+                }
+            }
             if (e < e1) {
-                v = g.col[e];
-                w = g.W[e];
                 h = arc_hash((uint32_t)u, (uint32_t)v);
                 int lo, hi;
                 candidate_range(sX, sT, J, h, w, lo, hi);
