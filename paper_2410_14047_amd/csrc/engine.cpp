@@ -398,18 +398,25 @@ private:
     hipEvent_t ev_[2 * kMaxRounds] = {};
     hipEvent_t ph_[4] = {};  // sweep phase start/end, cascade phase start/end
     // graph mode: the instantiated graph of the last captured tick structure
-    hipGraph_t graph_ = nullptr;
-    hipGraphExec_t graph_exec_ = nullptr;
-    std::vector<int64_t> graph_key_;
+    // graph mode: instantiated graphs of recent step structures (least
+    // recently used dropped first)
+    struct CachedGraph {
+        std::vector<int64_t> key;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        int64_t last_use = 0;
+    };
+    static constexpr size_t kGraphCache = 8;
+    std::vector<CachedGraph> graphs_;
     hipStream_t gstream_ = nullptr;  // private stream for graphs when the engine's stream is the null stream
     int64_t graphs_built_ = 0, graph_replays_ = 0, steps_ = 0;
     void drop_graph()
     {
-        if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
-        if (graph_) (void)hipGraphDestroy(graph_);
-        graph_exec_ = nullptr;
-        graph_ = nullptr;
-        graph_key_.clear();
+        for (CachedGraph& c : graphs_) {
+            if (c.exec) (void)hipGraphExecDestroy(c.exec);
+            if (c.graph) (void)hipGraphDestroy(c.graph);
+        }
+        graphs_.clear();
     }
     im_tuning tune_{0, 0, 8, 16, 0};
 };
@@ -674,8 +681,17 @@ im_status Engine::step()
         // stream then (implicitly ordered with the null stream)
         if (!st_ && !gstream_) IMX_HIP(hipStreamCreate(&gstream_));
         cs = st_ ? st_ : gstream_;
-        if (!graph_exec_ || key != graph_key_) {  // capture this structure once
-            drop_graph();
+        CachedGraph* hit = nullptr;
+        for (CachedGraph& c : graphs_)
+            if (c.key == key) hit = &c;
+        if (!hit) {  // capture this structure once
+            if (graphs_.size() >= kGraphCache) {  // drop the least recently used
+                auto lru = std::min_element(graphs_.begin(), graphs_.end(),
+                                            [](const CachedGraph& x, const CachedGraph& y) { return x.last_use < y.last_use; });
+                if (lru->exec) (void)hipGraphExecDestroy(lru->exec);
+                if (lru->graph) (void)hipGraphDestroy(lru->graph);
+                graphs_.erase(lru);
+            }
             IMX_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
             const hipError_t e = issue(false, cs);
             hipGraph_t g = nullptr;
@@ -685,12 +701,20 @@ im_status Engine::step()
                 return set_error(IM_EDEVICE, std::string("graph capture: ") +
                                                  hipGetErrorString(e != hipSuccess ? e : e2));
             }
-            graph_ = g;
-            IMX_HIP(hipGraphInstantiate(&graph_exec_, graph_, nullptr, nullptr, 0));
-            graph_key_ = key;
+            CachedGraph c;
+            c.key = key;
+            c.graph = g;
+            const hipError_t ei = hipGraphInstantiate(&c.exec, g, nullptr, nullptr, 0);
+            if (ei != hipSuccess) {
+                (void)hipGraphDestroy(g);
+                return set_error(IM_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+            }
+            graphs_.push_back(c);
+            hit = &graphs_.back();
             ++graphs_built_;
         }
-        IMX_HIP(hipGraphLaunch(graph_exec_, cs));
+        hit->last_use = steps_;
+        IMX_HIP(hipGraphLaunch(hit->exec, cs));
         ++graph_replays_;
     } else {
         IMX_HIP(issue(true, st_));
