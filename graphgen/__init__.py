@@ -182,13 +182,33 @@ def trivalency_p(g: Graph, seed: int = 2) -> np.ndarray:
     return choices[rng.integers(0, 3, size=g.m)]
 
 
+def normal_p(g: Graph, mean: float = 0.05, sd: float = 0.025, seed: int = 2) -> np.ndarray:
+    """Per-arc probabilities drawn from N(mean, sd), clipped to [0, 1]: the
+    mixed-weight setting N0.05 of the paper's experiments (Section 5, edge
+    weight settings)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.clip(rng.normal(mean, sd, size=g.m), 0.0, 1.0).astype(np.float32)
+
+
+def uniform_range_p(g: Graph, lo: float = 0.0, hi: float = 0.1, seed: int = 2) -> np.ndarray:
+    """Per-arc probabilities drawn uniformly from [lo, hi): the setting U0.1 of
+    the paper's experiments (Section 5, edge weight settings)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.uniform(lo, hi, size=g.m).astype(np.float32)
+
+
 def with_p(g: Graph, scheme: str, seed: int = 2) -> Graph:
     """Return a shallow copy of g carrying the named probability scheme:
-    'wc', 'trivalency', or a float literal such as '0.01'."""
+    'wc', 'trivalency', 'normal' (N(0.05, 0.025) clipped to [0, 1]),
+    'uniform01' (U(0, 0.1)), or a float literal such as '0.01'."""
     if scheme == "wc":
         p = weighted_cascade_p(g)
     elif scheme == "trivalency":
         p = trivalency_p(g, seed)
+    elif scheme == "normal":
+        p = normal_p(g, seed=seed)
+    elif scheme == "uniform01":
+        p = uniform_range_p(g, seed=seed)
     else:
         p = uniform_p(g, float(scheme))
     return Graph(n=g.n, rowptr=g.rowptr, col=g.col, p=p, name=f"{g.name}_{scheme}")

@@ -387,3 +387,42 @@ def test_greedy_quality_against_exact_greedy(orc):
             covered[j] |= reach[j][b]
     exact = sum(len(c) for c in covered) / J
     assert r["spread"] >= 0.9 * exact
+
+
+def _mc_spread(g, seeds, R, rng):
+    """Expected IC spread of `seeds` by Monte-Carlo over R independent worlds
+    (standard RNG, every arc live with its own probability), by frontier
+    propagation over all worlds at once."""
+    src = g.src()
+    order = np.argsort(g.col, kind="stable")
+    dst_sorted = g.col[order]
+    starts = np.flatnonzero(np.r_[True, dst_sorted[1:] != dst_sorted[:-1]])
+    heads = dst_sorted[starts]
+    live = rng.random((R, g.m)) < g.p[None, :]
+    reach = np.zeros((R, g.n), dtype=bool)
+    reach[:, seeds] = True
+    while True:
+        contrib = (reach[:, src] & live)[:, order]
+        hit = np.logical_or.reduceat(contrib, starts, axis=1)
+        new = reach.copy()
+        new[:, heads] |= hit
+        if np.array_equal(new, reach):
+            break
+        reach = new
+    sizes = reach.sum(axis=1)
+    return sizes.mean(), sizes.std()
+
+
+@pytest.mark.parametrize("scheme", ["0.1", "normal", "uniform01", "wc"])
+def test_spread_matches_independent_monte_carlo(orc, scheme):
+    """T/J of the chosen seeds (hash-decided worlds, Eq. 2) agrees with an
+    independent Monte-Carlo estimate of the IC spread of the same seeds.  The
+    bound is loose on purpose: XOR sampling correlates worlds of arcs whose
+    hashes share high bits, so the J worlds are not independent."""
+    g = graphgen.with_p(graphgen.erdos_renyi(300, 1500, 21), scheme)
+    J, K = 1024, 5
+    ref = orc.greedy(g, J, 3, K, keep_registers=False)
+    sk = ref["spread"]
+    mc, sd = _mc_spread(g, ref["seeds"], 10_000, np.random.default_rng(8))
+    tol = 3.0 * 4.0 * sd / np.sqrt(J) + 4.0 * sd / np.sqrt(10_000) + 0.5
+    assert abs(sk - mc) <= tol, (scheme, sk, mc, tol)

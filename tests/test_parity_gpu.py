@@ -78,6 +78,8 @@ CASES = {
     "er100_p0_J64": (lambda: graphgen.with_p(graphgen.erdos_renyi(100, 500, 7), "0"), 64, 13, 4),
     "cycle50_p1_J64": (lambda: _cycle(50), 64, 14, 5),
     "er60_p1_J128_Kn": (lambda: graphgen.with_p(graphgen.erdos_renyi(60, 150, 8), "1.0"), 128, 15, 60),
+    "er400_normal_J128": (lambda: graphgen.with_p(graphgen.erdos_renyi(400, 4000, 9), "normal"), 128, 16, 8),
+    "rmat11_uniform01_J256": (lambda: graphgen.with_p(graphgen.rmat(11, 16, seed=4), "uniform01"), 256, 17, 6),
 }
 
 
