@@ -220,7 +220,9 @@ im_status im_engine_create(int32_t max_queries, uint64_t hbm_budget_bytes, void*
  *   group_first, group_rest  lanes per propagation task (16, 32 or 64) in the
  *                            first sweep after a fill and in later sweeps, or
  *                            0 for the packed kernel (each wave takes
- *                            max(1, min(16, 2048 / J)) tasks at once);
+ *                            max(1, min(16, B / J)) tasks at once, B = 2048
+ *                            bytes, or 1024 / 4096 from the environment
+ *                            variable IMX_PACK_BYTES, read once per process);
  *   rounds_per_step          sweeps / cascade levels launched per step (1..16);
  *   dense_div                a sweep visits every task instead of an active
  *                            list when more than n / dense_div rows changed in

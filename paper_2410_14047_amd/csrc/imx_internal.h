@@ -11,11 +11,33 @@ constexpr int kWaves = 4;             // waves per workgroup in the wave-per-tas
 constexpr int kWG = 64 * kWaves;      // workgroup size
 constexpr int kMaxJ = 4096;           // registers per vertex, upper bound
 constexpr int kArgmaxBlocks = 1024;   // partial-argmax workgroups
-constexpr int kBuckets = 1024;        // bucket table over the top bits of the 31-bit X values
-constexpr int kBucketShift = 21;      // X >> 21 selects the bucket
+constexpr int kBuckets = 256;         // bucket table over the top bits of the 31-bit X values
+constexpr int kBucketShift = 23;      // X >> 23 selects the bucket
 // LDS words of the X values plus bucket table, padded to 16 bytes so that the
 // per-wave and per-group areas after it keep 8- and 16-byte alignment.
 constexpr int kTableWords = ((kBuckets + 1 + 3) / 4) * 4;
+
+// Pointers in the records below point to device memory.  A record has two
+// views with one layout: the host view (G = false, plain pointers), which host
+// code fills, and the kernels' view (G = true), whose pointers carry the
+// global address space in device code.  Accesses through them compile to
+// global_* instructions rather than flat_* ones; a flat access also counts
+// against the LDS wait counter, so every wait for an LDS result would also
+// wait for the global loads in flight and undo their prefetching.
+template <class T, bool G>
+struct dptr_s {
+    using type = T*;
+};
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+struct dptr_s<T, true> {
+    using type = __attribute__((address_space(1))) T*;
+};
+#endif
+template <class T, bool G>
+using dptr = typename dptr_s<T, G>::type;
+template <class T>
+using gptr = dptr<T, true>;
 
 // Device view of a loaded graph and its work decomposition.
 //   Out-tasks: every vertex u with out-degree > 0 owns the tasks
@@ -23,25 +45,27 @@ constexpr int kTableWords = ((kBuckets + 1 + 3) / 4) * 4;
 //   consecutive out-arcs starting at task_e0[t].
 //   In-tasks: the same over the reverse graph (in-arcs of v, sources in
 //   in_col), runs of at most `in_split` in-arcs.
-struct GraphDev {
+template <bool G>
+struct GraphDevT {
     int64_t n, m;
-    const int64_t* rowptr;        // [n+1]
-    const int32_t* col;           // [m]
-    const uint32_t* W;            // [m] 31-bit fixed-point thresholds
-    const int32_t* task_u;        // [ntasks]
-    const int64_t* task_e0;       // [ntasks]
-    const uint32_t* task_len;     // [ntasks] arcs in the task; bit 31 set when u has several tasks
-    const int32_t* task_start;    // [n+1]
+    dptr<const int64_t, G> rowptr;        // [n+1]
+    dptr<const int32_t, G> col;           // [m]
+    dptr<const uint32_t, G> W;            // [m] 31-bit fixed-point thresholds
+    dptr<const int32_t, G> task_u;        // [ntasks]
+    dptr<const int64_t, G> task_e0;       // [ntasks]
+    dptr<const uint32_t, G> task_len;     // [ntasks] arcs in the task; bit 31 set when u has several tasks
+    dptr<const int32_t, G> task_start;    // [n+1]
     int64_t ntasks;
     int32_t split;
-    const int64_t* in_rowptr;     // [n+1]
-    const int32_t* in_col;        // [m] source of each in-arc
-    const int32_t* in_task_v;     // [n_in_tasks]
-    const int64_t* in_task_e0;    // [n_in_tasks]
-    const int32_t* in_task_start; // [n+1]
+    dptr<const int64_t, G> in_rowptr;     // [n+1]
+    dptr<const int32_t, G> in_col;        // [m] source of each in-arc
+    dptr<const int32_t, G> in_task_v;     // [n_in_tasks]
+    dptr<const int64_t, G> in_task_e0;    // [n_in_tasks]
+    dptr<const int32_t, G> in_task_start; // [n+1]
     int64_t n_in_tasks;
     int32_t in_split;
 };
+using GraphDev = GraphDevT<false>;
 
 // Device state of the propagation sweeps.  Sweep s reads chg[s&1] (rows that
 // changed in sweep s-1) and the active task list act_tasks[s&1] (count
@@ -50,33 +74,37 @@ struct GraphDev {
 // sweep s flags the sources of those in-arcs in act8 (plain byte stores), and
 // the prep step of sweep s+1 compacts the flags into act_tasks[(s+1)&1] /
 // act_count[(s+1)&3], clearing them.
-struct SweepDev {
-    int32_t* act_tasks[2];            // [ntasks] each
-    uint32_t* act_count;              // [4]
-    uint32_t* chg[2];                 // [ceil(n/32)] each
-    uint8_t* act8;                    // [flag_bytes(n)] vertex activated for the next sweep; all 0 between sweeps
-    int32_t* chg_list;                // [n_in_tasks]
-    uint32_t* chg_count;              // [4]
-    unsigned long long* rows_changed; // [4]
-    uint32_t* dense;                  // [4] sweep s visits every task when dense[s&3] != 0
-    uint32_t* conv;                   // first sweep of the build that changed no row (~0u: none yet);
+template <bool G>
+struct SweepDevT {
+    dptr<int32_t, G> act_tasks[2];            // [ntasks] each
+    dptr<uint32_t, G> act_count;              // [4]
+    dptr<uint32_t, G> chg[2];                 // [ceil(n/32)] each
+    dptr<uint8_t, G> act8;                    // [flag_bytes(n)] vertex activated for the next sweep; all 0 between sweeps
+    dptr<int32_t, G> chg_list;                // [n_in_tasks]
+    dptr<uint32_t, G> chg_count;              // [4]
+    dptr<unsigned long long, G> rows_changed; // [4]
+    dptr<uint32_t, G> dense;                  // [4] sweep s visits every task when dense[s&3] != 0
+    dptr<uint32_t, G> conv;                   // first sweep of the build that changed no row (~0u: none yet);
                                       // kernels of later sweeps return at once
 };
+using SweepDev = SweepDevT<false>;
 
 // Device state of the covering cascade (union-frontier BFS over tasks).
 // Level t flags the vertices it newly covers in lv8 (plain byte stores); the
 // compaction after level t turns the flags into frontier Q_{t+1} and the
 // touched list, clearing them.
-struct CascadeDev {
-    int32_t* q[2];           // frontier out-task lists, capacity ntasks each
-    uint32_t* qsize;         // ring of 4 list-size counters
-    uint8_t* lv8;            // [flag_bytes(n)] covered at the current level; all 0 between levels
-    int32_t* touched;        // [n] distinct vertices touched by this cascade
-    uint32_t* ntouched;      // counter for `touched`
-    uint32_t* touch_stamp;   // [n] id of the last cascade that touched v
-    unsigned long long* T;   // covered (vertex, simulation) pairs
-    uint32_t* level_end;     // first level of the cascade with an empty frontier (~0u: running)
+template <bool G>
+struct CascadeDevT {
+    dptr<int32_t, G> q[2];           // frontier out-task lists, capacity ntasks each
+    dptr<uint32_t, G> qsize;         // ring of 4 list-size counters
+    dptr<uint8_t, G> lv8;            // [flag_bytes(n)] covered at the current level; all 0 between levels
+    dptr<int32_t, G> touched;        // [n] distinct vertices touched by this cascade
+    dptr<uint32_t, G> ntouched;      // counter for `touched`
+    dptr<uint32_t, G> touch_stamp;   // [n] id of the last cascade that touched v
+    dptr<unsigned long long, G> T;   // covered (vertex, simulation) pairs
+    dptr<uint32_t, G> level_end;     // first level of the cascade with an empty frontier (~0u: running)
 };
+using CascadeDev = CascadeDevT<false>;
 
 // Row-streaming kernels (fill, estimate) give each row an aligned group of L
 // lanes, L the largest power of two not above min(64, J/16); each lane owns
@@ -90,12 +118,13 @@ __host__ __device__ inline int row_lanes(int J)
 // Rows a lane group of the row-streaming kernels handles together (loads in flight).
 constexpr int kRowBatch = 4;
 
-// Packed propagation kernel: a wave takes pack_rows(J)
-// tasks at once, staging kPackBytes of register rows (at least one row).
-constexpr int kPackBytes = 2048;
-__host__ __device__ inline int pack_rows(int J)
+// Packed propagation kernel: a wave takes pack_rows(J, pb) tasks at once,
+// staging pb bytes of register rows (at least one row); pb = pack_bytes(),
+// 1024, 2048 or 4096 (environment IMX_PACK_BYTES, read once).
+int pack_bytes();
+__host__ __device__ inline int pack_rows(int J, int pb)
 {
-    const int p = kPackBytes / J;
+    const int p = pb / J;
     return p < 1 ? 1 : (p > 16 ? 16 : p);
 }
 
@@ -114,11 +143,13 @@ struct PropCounters {
     unsigned long long rows_changed;   // distinct rows u that changed
 };
 
-struct ArgmaxScratch {
-    uint32_t* pJ;            // [kArgmaxBlocks]
-    unsigned long long* pH;  // [kArgmaxBlocks]
-    int32_t* pid;            // [kArgmaxBlocks]
+template <bool G>
+struct ArgmaxScratchT {
+    dptr<uint32_t, G> pJ;            // [kArgmaxBlocks]
+    dptr<unsigned long long, G> pH;  // [kArgmaxBlocks]
+    dptr<int32_t, G> pid;            // [kArgmaxBlocks]
 };
+using ArgmaxScratch = ArgmaxScratchT<false>;
 
 // ---------------------------------------------------------------------------
 // Batched launches.  One launch serves up to kMaxBatch queries: query i owns
@@ -132,106 +163,126 @@ struct Batch {
     int wg0[kMaxBatch + 1];
 };
 
-struct FillArgs {
-    uint8_t* M;
+template <bool G>
+struct FillArgsT {
+    dptr<uint8_t, G> M;
     int64_t n;
     int J;
     int first;  // fresh sketch: every register uncovered
     uint64_t seed;
 };
+using FillArgs = FillArgsT<false>;
 
-struct PrepArgs {
-    SweepDev s;
-    const int32_t* task_start;  // [n+1] out-tasks of each vertex
+template <bool G>
+struct PrepArgsT {
+    SweepDevT<G> s;
+    dptr<const int32_t, G> task_start;  // [n+1] out-tasks of each vertex
     int64_t n;
     int64_t nwords;
     int sweep;
 };
+using PrepArgs = PrepArgsT<false>;
 
-struct PropArgs {
-    GraphDev g;
-    const uint32_t* X;            // sorted values + bucket table
+template <bool G>
+struct PropArgsT {
+    GraphDevT<G> g;
+    dptr<const uint32_t, G> X;            // sorted values + bucket table
     int J;
-    uint8_t* M;
-    const int32_t* tasks;         // active tasks (nullptr: every task)
-    const uint32_t* task_count;   // device count of `tasks`
-    const uint32_t* chg_prev;
-    uint32_t* chg_next;
-    int32_t* chg_list;
-    uint32_t* chg_count;
-    const uint32_t* dense;        // nonzero: visit every task this sweep
-    const uint32_t* conv;         // the build converged before this sweep when != ~0u
-    unsigned long long* rows_changed;
-    PropCounters* stats;          // instrumented variant only
-    uint32_t* vstamp;             // instrumented variant only: [n] last launch id that counted row u
+    dptr<uint8_t, G> M;
+    dptr<const int32_t, G> tasks;         // active tasks (nullptr: every task)
+    dptr<const uint32_t, G> task_count;   // device count of `tasks`
+    dptr<const uint32_t, G> chg_prev;
+    dptr<uint32_t, G> chg_next;
+    dptr<int32_t, G> chg_list;
+    dptr<uint32_t, G> chg_count;
+    dptr<const uint32_t, G> dense;        // nonzero: visit every task this sweep
+    dptr<const uint32_t, G> conv;         // the build converged before this sweep when != ~0u
+    dptr<unsigned long long, G> rows_changed;
+    dptr<PropCounters, G> stats;          // instrumented variant only
+    dptr<uint32_t, G> vstamp;             // instrumented variant only: [n] last launch id that counted row u
     uint32_t stamp_id;            // instrumented variant only: id of this launch (increasing)
 };
+using PropArgs = PropArgsT<false>;
 
-struct MarkArgs {
-    GraphDev g;
-    SweepDev s;
+template <bool G>
+struct MarkArgsT {
+    GraphDevT<G> g;
+    SweepDevT<G> s;
     int sweep;
     int dense_div;  // next sweep visits every task when more than n / dense_div rows changed
 };
+using MarkArgs = MarkArgsT<false>;
 
-struct EstArgs {
-    const uint8_t* M;
+template <bool G>
+struct EstArgsT {
+    dptr<const uint8_t, G> M;
     int64_t n;
     int J;
-    uint32_t* Ju;
-    unsigned long long* Hu;
+    dptr<uint32_t, G> Ju;
+    dptr<unsigned long long, G> Hu;
 };
+using EstArgs = EstArgsT<false>;
 
-struct ArgmaxArgs {
-    const uint32_t* Ju;
-    const unsigned long long* Hu;
-    const uint8_t* is_seed;
+template <bool G>
+struct ArgmaxArgsT {
+    dptr<const uint32_t, G> Ju;
+    dptr<const unsigned long long, G> Hu;
+    dptr<const uint8_t, G> is_seed;
     int64_t n;
-    ArgmaxScratch am;
-    int32_t* best;
+    ArgmaxScratchT<G> am;
+    dptr<int32_t, G> best;
     int nparts;  // workgroups of the partial pass for this query
 };
+using ArgmaxArgs = ArgmaxArgsT<false>;
 
-struct SeedArgs {
-    GraphDev g;
-    const int32_t* best;
+template <bool G>
+struct SeedArgsT {
+    GraphDevT<G> g;
+    dptr<const int32_t, G> best;
     int32_t k;
-    uint8_t* M;
+    dptr<uint8_t, G> M;
     int J;
-    uint8_t* is_seed;
-    int32_t* seeds;
-    uint32_t* pickJ;
-    unsigned long long* pickH;
-    const uint32_t* Ju;
-    const unsigned long long* Hu;
-    CascadeDev c;
+    dptr<uint8_t, G> is_seed;
+    dptr<int32_t, G> seeds;
+    dptr<uint32_t, G> pickJ;
+    dptr<unsigned long long, G> pickH;
+    dptr<const uint32_t, G> Ju;
+    dptr<const unsigned long long, G> Hu;
+    CascadeDevT<G> c;
     uint32_t cascade_id;
 };
+using SeedArgs = SeedArgsT<false>;
 
-struct LevelArgs {
-    GraphDev g;
-    const uint32_t* X;
+template <bool G>
+struct LevelArgsT {
+    GraphDevT<G> g;
+    dptr<const uint32_t, G> X;
     int J;
-    uint8_t* M;
-    CascadeDev c;
+    dptr<uint8_t, G> M;
+    CascadeDevT<G> c;
     int t;
 };
+using LevelArgs = LevelArgsT<false>;
 
-struct LevelCompactArgs {
-    const int32_t* task_start;  // [n+1]
+template <bool G>
+struct LevelCompactArgsT {
+    dptr<const int32_t, G> task_start;  // [n+1]
     int64_t n;
-    CascadeDev c;
+    CascadeDevT<G> c;
     int t;                // the level whose flags are compacted into Q_{t+1}
     uint32_t cascade_id;
 };
+using LevelCompactArgs = LevelCompactArgsT<false>;
 
-struct FinArgs {
-    uint8_t* M;
+template <bool G>
+struct FinArgsT {
+    dptr<uint8_t, G> M;
     int J;
-    uint32_t* Ju;
-    unsigned long long* Hu;
-    CascadeDev c;
+    dptr<uint32_t, G> Ju;
+    dptr<unsigned long long, G> Hu;
+    CascadeDevT<G> c;
 };
+using FinArgs = FinArgsT<false>;
 
 int device_cu_count();
 int propagate_group_size(int J, int requested);

@@ -9,6 +9,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
 #include <mutex>
 
 namespace imx {
@@ -212,6 +213,11 @@ __device__ __forceinline__ uint32_t pack4(uint4 w) { return w.x | (w.y << 8) | (
 // takes one atomic per batch instead of one per append.
 constexpr int kWaveBufCap = 256;
 
+// Value of x in lane l, l the same in every lane: a scalar read of the
+// register instead of a permute through LDS.
+__device__ __forceinline__ int lane_val(int x, int l) { return __builtin_amdgcn_readlane(x, l); }
+__device__ __forceinline__ uint32_t lane_val(uint32_t x, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)x, l); }
+
 struct WaveList {
     int32_t* buf;   // LDS staging area of `cap` entries
     int n;          // staged entries (wave-uniform)
@@ -226,7 +232,7 @@ __device__ __forceinline__ void wl_flush(WaveList& w)
     wave_lds_sync();
     uint32_t base = 0;
     if (lane_id() == 0) base = atomicAdd(w.ctr, (uint32_t)w.n);
-    base = __shfl(base, 0, 64);
+    base = lane_val(base, 0);
     for (int i = lane_id(); i < w.n; i += 64) w.L[base + i] = w.buf[i];
     w.n = 0;
     wave_lds_sync();
@@ -237,12 +243,12 @@ __device__ __forceinline__ void wl_append_ranges(WaveList& w, int cnt, int32_t f
 {
     const int lane = lane_id();
     const int incl = wave_incl_scan(cnt);
-    const int total = __shfl(incl, 63, 64);
+    const int total = lane_val(incl, 63);
     if (total == 0) return;
     if (total > w.cap) {
         uint32_t base = 0;
         if (lane == 63) base = atomicAdd(w.ctr, (uint32_t)total);
-        base = __shfl(base, 63, 64);
+        base = lane_val(base, 63);
         const uint32_t off = base + (uint32_t)(incl - cnt);
         for (int q = 0; q < cnt; ++q) w.L[off + q] = first + q;
         return;
@@ -261,7 +267,7 @@ __device__ __forceinline__ void wl_append_uniform(WaveList& w, int cnt, int32_t 
     if (cnt > w.cap) {
         uint32_t base = 0;
         if (lane == 0) base = atomicAdd(w.ctr, (uint32_t)cnt);
-        base = __shfl(base, 0, 64);
+        base = lane_val(base, 0);
         for (int q = lane; q < cnt; q += 64) w.L[base + q] = first + q;
         return;
     }
@@ -406,9 +412,17 @@ __device__ __forceinline__ int batch_index(const Batch& B)
     return i;
 }
 
+// The kernels' view of a host-filled argument record (same layout; its
+// pointers carry the global address space).
+template <template <bool> class S>
+__device__ __forceinline__ const S<true>& gview(const S<false>& x)
+{
+    return reinterpret_cast<const S<true>&>(x);
+}
+
 #define IMX_BATCH_PROLOGUE(ArgsT)                                     \
     const int bi_ = batch_index(B);                                   \
-    const ArgsT& a = args[bi_];                                       \
+    const auto& a = gview(args[bi_]);                                 \
     const int64_t lb = (int64_t)blockIdx.x - B.wg0[bi_];              \
     const int64_t lg = (int64_t)B.wg0[bi_ + 1] - B.wg0[bi_];          \
     (void)lb;                                                         \
@@ -687,7 +701,7 @@ __global__ __launch_bounds__(kWG, 6) void k_propagate(const PropArgs* __restrict
     unsigned long long c_tasks = 0, c_rows = 0, c_wbytes = 0, c_scanned = 0, c_active = 0, c_sectors = 0;
     unsigned long long c_changed = 0, c_visited = 0;
 
-    const GraphDev& g = a.g;
+    const auto& g = a.g;
     // every task after a fill or after a sweep that changed many rows; else the active list
     const bool sweep0 = a.tasks == nullptr;  // right after a fill every head counts as changed
     const bool all = sweep0 || *a.dense != 0u;
@@ -983,28 +997,41 @@ constexpr int kPackMax = 16;
 // sector masks (2 x 64, instrumented variant), list buffer.
 constexpr int kPackArcWords = 6 * 64;
 constexpr int kPackTaskWords = 10 * kPackMax + 16;
-__host__ __device__ inline int pack_row_words(int maxJ) { return (maxJ / 4 > kPackBytes / 4) ? maxJ / 4 : kPackBytes / 4; }
-__host__ __device__ inline int pack_dirty_words(int maxJ) { return pack_row_words(maxJ) / 4; }  // one byte per row word
+__host__ __device__ inline int pack_row_words(int maxJ, int pb) { return (maxJ > pb) ? maxJ / 4 : pb / 4; }
+__host__ __device__ inline int pack_dirty_words(int maxJ, int pb) { return pack_row_words(maxJ, pb) / 4; }  // a byte per row word
 constexpr int kPackBufCap = 128;  // staging entries per wave for the changed in-task list
-__host__ __device__ inline int pack_wave_words(int maxJ)
+__host__ __device__ inline int pack_wave_words(int maxJ, int pb, bool stats)
 {
-    return pack_row_words(maxJ) + pack_dirty_words(maxJ) + kPackArcWords + kPackTaskWords + 2 * 64 + kPackBufCap;
+    return pack_row_words(maxJ, pb) + pack_dirty_words(maxJ, pb) + kPackArcWords + kPackTaskWords + (stats ? 2 * 64 : 0) +
+           kPackBufCap;
 }
 
-// Five waves per SIMD: the LDS of a workgroup (about 31 KB at J <= 2048)
-// admits five workgroups per CU, so registers may use that occupancy's share.
+int pack_bytes()
+{
+    static const int pb = [] {
+        const char* v = std::getenv("IMX_PACK_BYTES");
+        const int b = v ? std::atoi(v) : 2048;
+        return (b == 1024 || b == 2048 || b == 4096) ? b : 2048;
+    }();
+    return pb;
+}
+
+// Six waves per SIMD: the LDS of a workgroup (about 24 KB at J = 512 with
+// 2 KB packs) admits six workgroups per CU, and registers are held to that
+// occupancy's share (measured faster than five waves with more registers, and
+// than seven or eight waves with spills).
 template <bool STATS>
-__global__ __launch_bounds__(kWG, 5) void k_propagate_pack(const PropArgs* __restrict__ args, Batch B, int maxJ)
+__global__ __launch_bounds__(kWG, 6) void k_propagate_pack(const PropArgs* __restrict__ args, Batch B, int maxJ, int pb)
 {
     IMX_BATCH_PROLOGUE(PropArgs);
     extern __shared__ uint32_t smem[];
     const int J = a.J;
     const int Jw = J >> 2;
-    const int P = pack_rows(J);
+    const int P = pack_rows(J, pb);
     const int wave = (int)(threadIdx.x >> 6);
     const int lane = lane_id();
 
-    const GraphDev& g = a.g;
+    const auto& g = a.g;
     const bool sweep0 = a.tasks == nullptr;
     const bool all = sweep0 || *a.dense != 0u;
     const int32_t* tasks = all ? nullptr : a.tasks;
@@ -1016,10 +1043,11 @@ __global__ __launch_bounds__(kWG, 5) void k_propagate_pack(const PropArgs* __res
     uint32_t* sX = smem;
     const uint32_t* sT = smem + J;
     const int XT = ((maxJ + kTableWords) + 3) & ~3;
-    uint32_t* wbase = smem + XT + wave * pack_wave_words(maxJ);
+    const int rw = pack_row_words(maxJ, pb), dw8 = pack_dirty_words(maxJ, pb);
+    uint32_t* wbase = smem + XT + wave * pack_wave_words(maxJ, pb, STATS);
     uint32_t* rows = wbase;                                      // P x Jw words
-    uint8_t* dirty8 = reinterpret_cast<uint8_t*>(rows + pack_row_words(maxJ));  // P x Jw bytes
-    int* ev = reinterpret_cast<int*>(rows + pack_row_words(maxJ) + pack_dirty_words(maxJ));
+    uint8_t* dirty8 = reinterpret_cast<uint8_t*>(rows + rw);     // P x Jw bytes
+    int* ev = reinterpret_cast<int*>(rows + rw + dw8);
     uint32_t* eh = reinterpret_cast<uint32_t*>(ev + 64);
     uint32_t* eW = eh + 64;
     int* edl = reinterpret_cast<int*>(eW + 64);
@@ -1035,10 +1063,10 @@ __global__ __launch_bounds__(kWG, 5) void k_propagate_pack(const PropArgs* __res
     int* T_chg = T_act + kPackMax;
     int* T_in0 = T_chg + kPackMax;
     int* T_inc = T_in0 + kPackMax;
-    unsigned long long* esec =
-        reinterpret_cast<unsigned long long*>(wbase + pack_row_words(maxJ) + pack_dirty_words(maxJ) + kPackArcWords +
-                                              kPackTaskWords);  // STATS only; 8-byte aligned (all counts even)
-    int32_t* wbuf = reinterpret_cast<int32_t*>(esec + 64);
+    unsigned long long* esec = reinterpret_cast<unsigned long long*>(wbase + rw + dw8 + kPackArcWords +
+                                                                     kPackTaskWords);  // STATS only; 8-byte aligned
+    int32_t* wbuf = reinterpret_cast<int32_t*>(STATS ? reinterpret_cast<uint32_t*>(esec + 64)
+                                                     : reinterpret_cast<uint32_t*>(esec));
     WaveList chl{wbuf, 0, a.chg_list, a.chg_count, kPackBufCap};
     unsigned long long c_tasks = 0, c_rows = 0, c_wbytes = 0, c_scanned = 0, c_active = 0, c_sectors = 0;
     unsigned long long c_changed = 0, c_visited = 0;
@@ -1090,7 +1118,7 @@ __global__ __launch_bounds__(kWG, 5) void k_propagate_pack(const PropArgs* __res
         t_nx2 = task_id(pk + 2 * pstride);
         const int na = (t >= 0) ? (int)(len & 0x7fffffffu) : 0;
         const int incl = wave_incl_scan(na);
-        const int A = __shfl(incl, 63, 64);
+        const int A = lane_val(incl, 63);
         if (lane < P) {
             T_u[lane] = (t >= 0) ? u : -1;
             T_e0lo[lane] = (uint32_t)e0;
@@ -1173,9 +1201,9 @@ __global__ __launch_bounds__(kWG, 5) void k_propagate_pack(const PropArgs* __res
             while (rem) {
                 const int ak = __ffsll((long long)rem) - 1;
                 rem &= rem - 1ull;
-                const int vk = __shfl(v, ak, 64), kk = __shfl(k, ak, 64);
-                const uint32_t hk = __shfl(h, ak, 64), wk = __shfl(w, ak, 64);
-                const int lok = __shfl(lo, ak, 64), hik = __shfl(hi, ak, 64);
+                const int vk = lane_val(v, ak), kk = lane_val(k, ak);
+                const uint32_t hk = lane_val(h, ak), wk = lane_val(w, ak);
+                const int lok = lane_val(lo, ak), hik = lane_val(hi, ak);
                 const uint32_t* src = M32 + (size_t)vk * (size_t)Jw;
                 uint32_t* rk = rows + kk * Jw;
                 for (int idx = lane; idx < Jw; idx += 64) {
@@ -1196,7 +1224,7 @@ __global__ __launch_bounds__(kWG, 5) void k_propagate_pack(const PropArgs* __res
 
             // sparse arcs: flattened (arc, word) items over the wave
             const int iincl = wave_incl_scan(nd);
-            const int total = __shfl(iincl, 63, 64);
+            const int total = lane_val(iincl, 63);
             if (total == 0) continue;
             ev[lane] = v;
             eh[lane] = h;
@@ -1373,11 +1401,11 @@ static hipError_t launch_propagate_t(const PropArgs* args, const Batch& B, int m
 // at most 16 words of the row per lane, unless a larger one is requested.
 // Lanes per task: the lane-group size (16, 32 or 64, at least what keeps 16
 // words of the row per lane), or for the packed kernel (requested 0) the
-// wave's 64 lanes shared by pack_rows(J) tasks.
+// wave's 64 lanes shared by pack_rows(J, pack_bytes()) tasks.
 int propagate_group_size(int J, int requested)
 {
     if (requested == 0) {
-        const int l = 64 / pack_rows(J);
+        const int l = 64 / pack_rows(J, pack_bytes());
         return l < 1 ? 1 : l;
     }
     int gs = (J <= 1024) ? 16 : (J <= 2048) ? 32 : 64;
@@ -1385,16 +1413,16 @@ int propagate_group_size(int J, int requested)
     return gs;
 }
 
-static size_t pack_lds(int maxJ)
+static size_t pack_lds(int maxJ, bool stats)
 {
     const int XT = ((maxJ + kTableWords) + 3) & ~3;
-    return sizeof(uint32_t) * ((size_t)XT + (size_t)kWaves * (size_t)pack_wave_words(maxJ));
+    return sizeof(uint32_t) * ((size_t)XT + (size_t)kWaves * (size_t)pack_wave_words(maxJ, pack_bytes(), stats));
 }
 
 template <bool STATS>
 static hipError_t pack_setup(int maxJ, int* per_cu)
 {
-    const size_t lds = pack_lds(maxJ);
+    const size_t lds = pack_lds(maxJ, STATS);
     std::lock_guard<std::mutex> lock(g_launch_cfg_mutex);
     static size_t lds_set = 0, attr_set = 0;
     static int cached = 0;
@@ -1454,11 +1482,12 @@ hipError_t launch_propagate(const PropArgs* args, const Batch& B, int maxJ, int 
         int per_cu = 0;
         hipError_t e = stats ? pack_setup<true>(maxJ, &per_cu) : pack_setup<false>(maxJ, &per_cu);
         if (e != hipSuccess) return e;
-        const size_t lds = pack_lds(maxJ);
+        const size_t lds = pack_lds(maxJ, stats);
+        const int pb = pack_bytes();
         if (stats)
-            hipLaunchKernelGGL(k_propagate_pack<true>, dim3(B.wg0[B.nq]), dim3(kWG), lds, st, args, B, maxJ);
+            hipLaunchKernelGGL(k_propagate_pack<true>, dim3(B.wg0[B.nq]), dim3(kWG), lds, st, args, B, maxJ, pb);
         else
-            hipLaunchKernelGGL(k_propagate_pack<false>, dim3(B.wg0[B.nq]), dim3(kWG), lds, st, args, B, maxJ);
+            hipLaunchKernelGGL(k_propagate_pack<false>, dim3(B.wg0[B.nq]), dim3(kWG), lds, st, args, B, maxJ, pb);
         return hipGetLastError();
     }
     return propagate_dispatch(maxJ, gs, stats, [&]<int G, int D, bool S>() -> hipError_t {
@@ -1474,7 +1503,7 @@ __global__ __launch_bounds__(kWG) void k_sweep_prep(const PrepArgs* __restrict__
 {
     IMX_BATCH_PROLOGUE(PrepArgs);
     __shared__ int32_t wbuf[kWaves][kWaveBufCap];
-    const SweepDev& s = a.s;
+    const auto& s = a.s;
     const int sweep = a.sweep;
     const int64_t i0 = lb * blockDim.x + threadIdx.x;
     if (sweep > 0 && *s.conv != ~0u) return;  // the build has converged
@@ -1510,8 +1539,8 @@ hipError_t launch_sweep_prep(const PrepArgs* args, const Batch& B, hipStream_t s
 __global__ __launch_bounds__(kWG) void k_mark(const MarkArgs* __restrict__ args, Batch B)
 {
     IMX_BATCH_PROLOGUE(MarkArgs);
-    const GraphDev& g = a.g;
-    const SweepDev& s = a.s;
+    const auto& g = a.g;
+    const auto& s = a.s;
     const int sweep = a.sweep;
     const int lane = lane_id();
     // Many changed rows (more than n / dense_div): the next sweep visits every
@@ -1727,8 +1756,8 @@ __device__ __forceinline__ bool uncovered(uint32_t b) { return b >= 1u && b <= 3
 __global__ __launch_bounds__(64) void k_cascade_seed(const SeedArgs* __restrict__ args, Batch B)
 {
     IMX_BATCH_PROLOGUE(SeedArgs);
-    const GraphDev& g = a.g;
-    const CascadeDev& c = a.c;
+    const auto& g = a.g;
+    const auto& c = a.c;
     const int lane = lane_id();
     const int32_t s = *a.best;
     if (s < 0) {  // no candidate (cannot happen for K <= n); leave an empty cascade
@@ -1836,7 +1865,7 @@ __global__ __launch_bounds__(kWG) void k_cascade_level(const LevelArgs* __restri
     uint8_t* lv8 = a.c.lv8;
     const uint32_t mk_prev = marker(a.t - 1);
     const uint32_t mk_cur = marker(a.t);
-    const GraphDev& g = a.g;
+    const auto& g = a.g;
     const uint32_t* M32 = reinterpret_cast<const uint32_t*>(a.M);
     const int64_t nw = lg * kWaves;
 
@@ -1897,7 +1926,7 @@ __global__ __launch_bounds__(kWG) void k_cascade_level(const LevelArgs* __restri
                 }
             }
             const int incl = wave_incl_scan(cnt);
-            const int total = __shfl(incl, 63, 64);
+            const int total = lane_val(incl, 63);
             if (total == 0) continue;
             ev[lane] = v;
             eh[lane] = h;
@@ -1973,7 +2002,7 @@ __global__ __launch_bounds__(kWG) void k_cascade_compact(const LevelCompactArgs*
 {
     IMX_BATCH_PROLOGUE(LevelCompactArgs);
     __shared__ int32_t wbuf[kWaves][2 * kWaveBufCap];
-    const CascadeDev& c = a.c;
+    const auto& c = a.c;
     if (c.qsize[a.t & 3] == 0u) return;  // empty level: nothing was flagged
     const int wave = (int)(threadIdx.x >> 6);
     WaveList L{wbuf[wave], 0, c.q[(a.t + 1) & 1], &c.qsize[(a.t + 1) & 3]};
@@ -2013,7 +2042,7 @@ __global__ __launch_bounds__(kWG) void k_cascade_finalize(const FinArgs* __restr
 {
     IMX_BATCH_PROLOGUE(FinArgs);
     __shared__ unsigned long long s_sum[kWaves];
-    const CascadeDev& c = a.c;
+    const auto& c = a.c;
     if (*c.level_end == ~0u) return;  // the cascade is still running (uniform)
     const int L = row_lanes(a.J);
     const int lane = lane_id();
