@@ -1038,7 +1038,7 @@ __global__ __launch_bounds__(kWG, 6) void k_propagate_pack(const PropArgs* __res
     const int64_t count = all ? g.ntasks : (int64_t)*a.task_count;
     const int64_t npacks = (count + P - 1) / P;
     if (*a.conv != ~0u) return;                // the build has converged
-    if (lb * kWaves >= npacks) return;          // no pack for this workgroup (uniform)
+    if (lb >= npacks) return;                   // no pack for this workgroup (uniform)
 
     uint32_t* sX = smem;
     const uint32_t* sT = smem + J;
@@ -1071,6 +1071,10 @@ __global__ __launch_bounds__(kWG, 6) void k_propagate_pack(const PropArgs* __res
     unsigned long long c_tasks = 0, c_rows = 0, c_wbytes = 0, c_scanned = 0, c_active = 0, c_sectors = 0;
     unsigned long long c_changed = 0, c_visited = 0;
 
+    // next draw of this workgroup's pack sequence: a padding word after the table
+    static_assert(kTableWords > kBuckets + 1, "the bucket table leaves a padding word");
+    uint32_t* const s_next = smem + (J + kBuckets + 1);
+    if (threadIdx.x == 0) *s_next = 2 * kWaves;
     for (int i = threadIdx.x; i < J + kBuckets + 1; i += kWG) sX[i] = a.X[i];
     __syncthreads();
 
@@ -1083,12 +1087,26 @@ __global__ __launch_bounds__(kWG, 6) void k_propagate_pack(const PropArgs* __res
 
     // Task records are loaded one pack ahead and task ids two packs ahead
     // (lanes 0..P-1 hold the pack's tasks).
-    const int64_t pstride = lg * kWaves;
     auto task_id = [&](int64_t pk) -> int32_t {
         const int64_t q = pk * P + lane;
         return (lane < P && pk < npacks && q < count) ? (tasks ? tasks[q] : (int32_t)q) : -1;
     };
-    int64_t pk = lb * kWaves + wave;
+    // Draw k of a workgroup is pack lb + k * lg (workgroups interleaved over
+    // the list).  A wave's first two draws are fixed (k = wave, wave + 4);
+    // later ones come from the workgroup's LDS counter, so the waves of a
+    // workgroup share its packs dynamically and a wave that met cheap packs
+    // takes more.  (A device-wide counter was measured 3-5x slower: atomics
+    // on one global address serialise.)  A draw is made two packs ahead and
+    // its task ids are loaded one pack ahead.
+    auto pack_of = [&](uint32_t k) -> int64_t { return lb + (int64_t)k * lg; };
+    auto draw = [&]() -> uint32_t {
+        uint32_t r = 0u;
+        if (lane == 0) r = atomicAdd(s_next, 1u);
+        return r;
+    };
+    int64_t pk = pack_of((uint32_t)wave);
+    int64_t pk_n1 = pack_of((uint32_t)(wave + kWaves)), pk_n2 = npacks;
+    uint32_t drawn = (pack_of(2 * kWaves) < npacks) ? draw() : ~0u;  // lane 0: the draw after pk_n1
     int32_t t_nx = task_id(pk);
     int32_t u_nx = 0;
     int64_t e0_nx = 0;
@@ -1098,8 +1116,8 @@ __global__ __launch_bounds__(kWG, 6) void k_propagate_pack(const PropArgs* __res
         e0_nx = g.task_e0[t_nx];
         len_nx = g.task_len[t_nx];
     }
-    int32_t t_nx2 = task_id(pk + pstride);
-    for (; pk < npacks; pk += pstride) {
+    int32_t t_nx2 = task_id(pk_n1);
+    for (; pk < npacks; pk = pk_n1, pk_n1 = pk_n2) {
         const int32_t t = t_nx, u = u_nx;
         const int64_t e0 = e0_nx;
         const uint32_t len = len_nx;
@@ -1115,7 +1133,9 @@ __global__ __launch_bounds__(kWG, 6) void k_propagate_pack(const PropArgs* __res
             e0_nx = g.task_e0[t_nx];
             len_nx = g.task_len[t_nx];
         }
-        t_nx2 = task_id(pk + 2 * pstride);
+        pk_n2 = pack_of(lane_val(drawn, 0));
+        drawn = (pk_n2 < npacks) ? draw() : ~0u;  // wave-uniform
+        t_nx2 = task_id(pk_n2);
         const int na = (t >= 0) ? (int)(len & 0x7fffffffu) : 0;
         const int incl = wave_incl_scan(na);
         const int A = lane_val(incl, 63);
