@@ -513,9 +513,10 @@ im_status Engine::step()
                             q->vstamp,
                             ++q->prop_launch_id};
                 Launch<PropArgs>& T = (s == 0) ? F : R;
-                const int lanes = propagate_group_size(q->J, s == 0 ? gs_first_ : gs_rest_);
+                const int gsel = s == 0 ? gs_first_ : gs_rest_;
+                const int lanes = propagate_group_size(q->J, gsel), thr = propagate_wg_threads(gsel);
                 T.args.push_back(pa);
-                T.want.push_back((q->g->ntasks * lanes + kWG - 1) / kWG);
+                T.want.push_back((q->g->ntasks * lanes + thr - 1) / thr);
                 T.maxJ = std::max(T.maxJ, q->J);
                 K.args.push_back(MarkArgs{gd, q->sw, s, tune_.dense_div});
                 K.want.push_back(std::min<int64_t>(cus * 4, (q->g->n_in_tasks + kWaves - 1) / kWaves));

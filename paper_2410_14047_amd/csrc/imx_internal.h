@@ -286,6 +286,7 @@ using FinArgs = FinArgsT<false>;
 
 int device_cu_count();
 int propagate_group_size(int J, int requested);
+int propagate_wg_threads(int requested);  // threads per workgroup of the propagation kernel chosen by `requested`
 hipError_t propagate_full_grid(int maxJ, int gs, bool stats, int* grid);
 hipError_t cascade_level_full_grid(int maxJ, int* grid);
 

@@ -991,6 +991,8 @@ __global__ __launch_bounds__(kWG, 6) void k_propagate(const PropArgs* __restrict
 
 
 constexpr int kPackMax = 16;
+constexpr int kPackWaves = 8;              // waves per workgroup of the packed kernel
+constexpr int kPackWG = 64 * kPackWaves;
 // LDS words per wave of the packed kernel besides the rows: dirty bytes,
 // per-arc arrays (ev, eh, eW, edl, est, ek: 6 x 64), task records (u, e0 lo/hi,
 // prefix, split, touched, active, changed, in_first, in_cnt: 10 x 16 + 1),
@@ -1016,12 +1018,13 @@ int pack_bytes()
     return pb;
 }
 
-// Six waves per SIMD: the LDS of a workgroup (about 24 KB at J = 512 with
-// 2 KB packs) admits six workgroups per CU, and registers are held to that
+// Eight waves per workgroup share the X table and the pack counter.  Six
+// waves per SIMD: the LDS of a workgroup (about 46 KB at J = 512 with 2 KB
+// packs) admits three workgroups per CU, and registers are held to that
 // occupancy's share (measured faster than five waves with more registers, and
 // than seven or eight waves with spills).
 template <bool STATS>
-__global__ __launch_bounds__(kWG, 6) void k_propagate_pack(const PropArgs* __restrict__ args, Batch B, int maxJ, int pb)
+__global__ __launch_bounds__(kPackWG, 3) void k_propagate_pack(const PropArgs* __restrict__ args, Batch B, int maxJ, int pb)
 {
     IMX_BATCH_PROLOGUE(PropArgs);
     extern __shared__ uint32_t smem[];
@@ -1074,8 +1077,8 @@ __global__ __launch_bounds__(kWG, 6) void k_propagate_pack(const PropArgs* __res
     // next draw of this workgroup's pack sequence: a padding word after the table
     static_assert(kTableWords > kBuckets + 1, "the bucket table leaves a padding word");
     uint32_t* const s_next = smem + (J + kBuckets + 1);
-    if (threadIdx.x == 0) *s_next = 2 * kWaves;
-    for (int i = threadIdx.x; i < J + kBuckets + 1; i += kWG) sX[i] = a.X[i];
+    if (threadIdx.x == 0) *s_next = 2 * kPackWaves;
+    for (int i = threadIdx.x; i < J + kBuckets + 1; i += kPackWG) sX[i] = a.X[i];
     __syncthreads();
 
     const uint32_t* M32 = reinterpret_cast<const uint32_t*>(a.M);
@@ -1092,7 +1095,7 @@ __global__ __launch_bounds__(kWG, 6) void k_propagate_pack(const PropArgs* __res
         return (lane < P && pk < npacks && q < count) ? (tasks ? tasks[q] : (int32_t)q) : -1;
     };
     // Draw k of a workgroup is pack lb + k * lg (workgroups interleaved over
-    // the list).  A wave's first two draws are fixed (k = wave, wave + 4);
+    // the list).  A wave's first two draws are fixed (k = wave, wave + 8);
     // later ones come from the workgroup's LDS counter, so the waves of a
     // workgroup share its packs dynamically and a wave that met cheap packs
     // takes more.  (A device-wide counter was measured 3-5x slower: atomics
@@ -1105,8 +1108,8 @@ __global__ __launch_bounds__(kWG, 6) void k_propagate_pack(const PropArgs* __res
         return r;
     };
     int64_t pk = pack_of((uint32_t)wave);
-    int64_t pk_n1 = pack_of((uint32_t)(wave + kWaves)), pk_n2 = npacks;
-    uint32_t drawn = (pack_of(2 * kWaves) < npacks) ? draw() : ~0u;  // lane 0: the draw after pk_n1
+    int64_t pk_n1 = pack_of((uint32_t)(wave + kPackWaves)), pk_n2 = npacks;
+    uint32_t drawn = (pack_of(2 * kPackWaves) < npacks) ? draw() : ~0u;  // lane 0: the draw after pk_n1
     int32_t t_nx = task_id(pk);
     int32_t u_nx = 0;
     int64_t e0_nx = 0;
@@ -1436,7 +1439,7 @@ int propagate_group_size(int J, int requested)
 static size_t pack_lds(int maxJ, bool stats)
 {
     const int XT = ((maxJ + kTableWords) + 3) & ~3;
-    return sizeof(uint32_t) * ((size_t)XT + (size_t)kWaves * (size_t)pack_wave_words(maxJ, pack_bytes(), stats));
+    return sizeof(uint32_t) * ((size_t)XT + (size_t)kPackWaves * (size_t)pack_wave_words(maxJ, pack_bytes(), stats));
 }
 
 template <bool STATS>
@@ -1453,7 +1456,7 @@ static hipError_t pack_setup(int maxJ, int* per_cu)
             if (err != hipSuccess) return err;
             attr_set = lds;
         }
-        hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&cached, k_propagate_pack<STATS>, kWG, lds);
+        hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&cached, k_propagate_pack<STATS>, kPackWG, lds);
         if (err != hipSuccess) return err;
         if (cached < 1) cached = 1;
         lds_set = lds;
@@ -1496,6 +1499,8 @@ hipError_t propagate_full_grid(int maxJ, int gs, bool stats, int* grid)
 
 int propagate_lanes_per_task(int maxJ, int gs) { return propagate_group_size(maxJ, gs); }
 
+int propagate_wg_threads(int gs) { return gs == 0 ? kPackWG : kWG; }
+
 hipError_t launch_propagate(const PropArgs* args, const Batch& B, int maxJ, int gs, bool stats, hipStream_t st)
 {
     if (gs == 0) {
@@ -1505,9 +1510,9 @@ hipError_t launch_propagate(const PropArgs* args, const Batch& B, int maxJ, int 
         const size_t lds = pack_lds(maxJ, stats);
         const int pb = pack_bytes();
         if (stats)
-            hipLaunchKernelGGL(k_propagate_pack<true>, dim3(B.wg0[B.nq]), dim3(kWG), lds, st, args, B, maxJ, pb);
+            hipLaunchKernelGGL(k_propagate_pack<true>, dim3(B.wg0[B.nq]), dim3(kPackWG), lds, st, args, B, maxJ, pb);
         else
-            hipLaunchKernelGGL(k_propagate_pack<false>, dim3(B.wg0[B.nq]), dim3(kWG), lds, st, args, B, maxJ, pb);
+            hipLaunchKernelGGL(k_propagate_pack<false>, dim3(B.wg0[B.nq]), dim3(kPackWG), lds, st, args, B, maxJ, pb);
         return hipGetLastError();
     }
     return propagate_dispatch(maxJ, gs, stats, [&]<int G, int D, bool S>() -> hipError_t {
