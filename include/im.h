@@ -234,7 +234,9 @@ im_status im_engine_create(int32_t max_queries, uint64_t hbm_budget_bytes, void*
  *                            launches.
  * Defaults: 0, 0, 8, 16, 0; the environment variables IMX_GROUP_FIRST,
  * IMX_GROUP, IMX_ROUNDS, IMX_DENSE_DIV and IMX_GRAPHS override them at engine
- * creation (an out-of-range value makes creation fail with IM_EINVAL). */
+ * creation (an out-of-range value makes creation fail with IM_EINVAL).
+ * IMX_PROP_GRID (>= 1), read at engine creation, caps the workgroups of a
+ * propagation launch (a test of schedule independence; never faster). */
 typedef struct im_tuning {
     int32_t group_first;
     int32_t group_rest;

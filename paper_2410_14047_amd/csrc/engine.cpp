@@ -136,6 +136,12 @@ public:
         if (const char* v = std::getenv("IMX_DENSE_DIV")) t.dense_div = std::atoi(v);
         if (const char* v = std::getenv("IMX_GRAPHS")) t.use_graphs = std::atoi(v);
         if (set_tuning(t) != IM_OK) return IM_EINVAL;
+        // Cap on the workgroups of a propagation launch (schedule tests: few
+        // workgroups make every one of them take many packs).
+        if (const char* v = std::getenv("IMX_PROP_GRID")) {
+            prop_grid_cap_ = std::atoi(v);
+            if (prop_grid_cap_ < 1) return set_error(IM_EINVAL, "IMX_PROP_GRID must be >= 1");
+        }
         IMX_HIP(hipStreamSynchronize(st_));
         return IM_OK;
     }
@@ -359,6 +365,8 @@ private:
 
     // Workgroup prefix for up to kMaxBatch queries, given per-query demands
     // and a cap on the launch's total (scaled down proportionally, >= 1 each).
+    int64_t prop_cap(int64_t full) const { return prop_grid_cap_ > 0 ? std::min<int64_t>(full, prop_grid_cap_) : full; }
+
     static Batch make_batch(const std::vector<int64_t>& want, int64_t cap)
     {
         Batch B{};
@@ -386,6 +394,7 @@ private:
     hipStream_t st_;
     int cap_;
     size_t budget_;
+    int64_t prop_grid_cap_ = 0;  // IMX_PROP_GRID (0: none)
     size_t used_ = 0;
     int64_t next_id_ = 1;
     std::vector<Query*> slots_;
@@ -606,8 +615,8 @@ im_status Engine::step()
     for (auto& L : L_fill) ok &= finish(0, L, 0);
     for (auto& R : rounds) {
         for (auto& L : R.prep) ok &= finish(1, L, 0);
-        for (auto& L : R.prop_first) ok &= finish(2, L, full_first);
-        for (auto& L : R.prop_rest) ok &= finish(3, L, full_rest);
+        for (auto& L : R.prop_first) ok &= finish(2, L, prop_cap(full_first));
+        for (auto& L : R.prop_rest) ok &= finish(3, L, prop_cap(full_rest));
         for (auto& L : R.mark) ok &= finish(4, L, (int64_t)cus * 4);
     }
     for (auto& L : L_est) ok &= finish(5, L, 0);

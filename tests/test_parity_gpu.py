@@ -142,6 +142,21 @@ def test_schedule_independence_of_split(imx, orc, monkeypatch):
         assert np.array_equal(a[key], b[key]), key
 
 
+@pytest.mark.parametrize("grid", ["1", "3"])
+@pytest.mark.parametrize("name", ["rmat12_wc_J512", "hub2000_p0.2_J256", "er150_p0.3_J4096", "er400_normal_J128"])
+def test_packed_kernel_on_few_workgroups(imx, orc, monkeypatch, name, grid):
+    """With the propagation grid capped at 1 or 3 workgroups, each workgroup
+    takes many packs and its waves draw them from the shared counter; the
+    results are the oracle's all the same."""
+    make, J, seed, K = CASES[name]
+    g = make()
+    monkeypatch.setenv("IMX_PROP_GRID", grid)
+    _say(f"[few workgroups {grid}] {name}")
+    ref = orc.greedy(g, J, seed, K)
+    gpu = run_gpu(imx, g, J, seed, K)
+    assert_parity(orc, gpu, ref, J, seed)
+
+
 def test_repeat_builds_identical(imx):
     g = graphgen.with_p(graphgen.rmat(11, 16, seed=5), "0.1")
     a = run_gpu(imx, g, 512, 2, 6)
