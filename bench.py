@@ -395,6 +395,7 @@ def main():
     load_ms = (time.perf_counter() - t_load) * 1e3
     J, K, seed = w["J"], w["K"], w["sseed"]
     step_ms = []
+    imx.im_set_profiling(1)  # per-launch kernel times (HIP events) in the timed steps
 
     def step():
         t = time.perf_counter()
@@ -452,7 +453,6 @@ def main():
         S = imx.Sketch(G, J, seed, stream=stream)
         rr = S.select(K)
         S.free()
-        imx.im_set_profiling(0)
         st = rr["stats"]
         assert list(rr["seeds"]) == list(results[0]["seeds"]), "instrumented run disagrees"
         bpl = st["prop_alg_bytes"] / st["prop_launches"]

@@ -54,13 +54,16 @@ typedef struct im_stats {
     double build_ms;         /* im_sketch_build: fill + propagation + estimate  */
     double select_ms;        /* im_select_seeds, end to end                     */
     double propagate_ms;     /* device time of the steps that ran this query's
-                                propagation sweeps (shared steps count fully)   */
+                                propagation sweeps (shared steps count fully;
+                                profiling level >= 1, else 0)                   */
     double cascade_ms;       /* device time of the steps that ran this query's
-                                covering cascades (shared steps count fully)    */
+                                covering cascades (shared steps count fully;
+                                profiling level >= 1, else 0)                   */
     int64_t prop_launches;   /* propagation kernel launches; a step launches a
                                 fixed number of sweeps, and those after the
                                 build converged return at once                  */
-    double prop_kernel_ms;   /* sum of per-launch propagation kernel times      */
+    double prop_kernel_ms;   /* sum of per-launch propagation kernel times
+                                (profiling level >= 1, else 0)                  */
     /* Algorithmic traffic of the propagation sweeps, counted by the kernel's
      * instrumented variant when profiling level 2 is on (else all 0):
      *   bytes = (8 + J)*rows_visited + J*rows_changed + 8*arcs_active + 64*sectors
@@ -102,11 +105,14 @@ typedef void (*im_free_fn)(void* ptr, void* ctx);
 im_status im_set_allocator(im_alloc_fn alloc, im_free_fn free_, void* ctx);
 
 /*
- * Process-wide measurement switch for sketches built afterwards:
- *   0  per-launch propagation kernel times only (HIP events; the default),
- *   2  additionally run the instrumented propagation kernel, which counts the
- *      algorithmic traffic reported in im_stats (slower; for roofline reports,
- *      never for timing).
+ * Process-wide measurement switch for engine steps issued afterwards:
+ *   0  no device timing (the default; propagate_ms, cascade_ms and
+ *      prop_kernel_ms in im_stats stay 0),
+ *   1  per-launch propagation kernel times and per-phase device times (HIP
+ *      events around the launches; not in HIP-graph mode),
+ *   2  as 1, and the instrumented propagation kernel runs, counting the
+ *      algorithmic traffic reported in im_stats (slower; for roofline
+ *      reports, never for timing).
  * Results are identical at every level.  Errors: IM_EINVAL for other levels.
  */
 im_status im_set_profiling(int32_t level);

@@ -110,7 +110,7 @@ im_status im_set_allocator(im_alloc_fn alloc, im_free_fn free_, void* ctx)
 
 im_status im_set_profiling(int32_t level)
 {
-    if (level != 0 && level != 2) return set_error(IM_EINVAL, "profiling level must be 0 or 2");
+    if (level < 0 || level > 2) return set_error(IM_EINVAL, "profiling level must be 0, 1 or 2");
     g_profiling.store(level);
     return IM_OK;
 }

@@ -126,8 +126,10 @@ public:
         args_cap_ = (size_t)cap_ * (kMaxRounds * 3 * 256 + 2048) + chunks * (kMaxRounds * 5 + 16) * 256;
         IMX_HIP(bufs_.alloc(&args_dev_, args_cap_));
         IMX_HIP(hipHostMalloc(reinterpret_cast<void**>(&args_host_), args_cap_, 0));
-        for (auto& e : ev_) IMX_HIP(hipEventCreate(&e));
-        for (auto& e : ph_) IMX_HIP(hipEventCreate(&e));
+        // timing-only events: no system-scope fence at record (a fenced record
+        // costs a cache write-back and invalidation between kernels)
+        for (auto& e : ev_) IMX_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+        for (auto& e : ph_) IMX_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
         // Environment overrides of the default tuning (validated like im_engine_set_tuning).
         im_tuning t = tune_;
         if (const char* v = std::getenv("IMX_GROUP_FIRST")) t.group_first = std::atoi(v);
@@ -682,6 +684,7 @@ im_status Engine::step()
     };
 
     const bool graph_mode = tune_.use_graphs != 0 && !stats;
+    const bool timed = !graph_mode && profiling_level() >= 1;  // per-launch and per-phase events
     hipStream_t cs = st_;  // stream of this tick's work
     if (graph_mode) {
         key.push_back((int64_t)args_off_);
@@ -727,15 +730,15 @@ im_status Engine::step()
         IMX_HIP(hipGraphLaunch(hit->exec, cs));
         ++graph_replays_;
     } else {
-        IMX_HIP(issue(true, st_));
+        IMX_HIP(issue(timed, st_));
     }
     IMX_HIP(hipStreamSynchronize(cs));
 
     float sweep_phase_ms = 0.f, cascade_phase_ms = 0.f;
-    if (!graph_mode && sweeping) (void)hipEventElapsedTime(&sweep_phase_ms, ph_[0], ph_[1]);
-    if (!graph_mode && cascading) (void)hipEventElapsedTime(&cascade_phase_ms, ph_[2], ph_[3]);
+    if (timed && sweeping) (void)hipEventElapsedTime(&sweep_phase_ms, ph_[0], ph_[1]);
+    if (timed && cascading) (void)hipEventElapsedTime(&cascade_phase_ms, ph_[2], ph_[3]);
     float prop_ms = 0.f;
-    for (int i = 0; i < (graph_mode ? 0 : ne); ++i) {
+    for (int i = 0; i < (timed ? ne : 0); ++i) {
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, ev_[2 * i], ev_[2 * i + 1]);
         prop_ms += ms;

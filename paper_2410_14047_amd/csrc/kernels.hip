@@ -1201,13 +1201,13 @@ __global__ __launch_bounds__(kPackWG, 3) void k_propagate_pack(const PropArgs* _
             if (base + 64 < A) arc_load(ai + 64, k_nx, v_nx, w_nx);
             int cnt = 0, lo = 0, hi = 0;
             uint32_t h = 0;
-            if (ai < A && w != 0u) {
+            // only arcs whose head changed in the previous sweep are hashed
+            const bool act_arc = ai < A && ((cw >> (v & 31)) & 1u);
+            if (act_arc && w != 0u) {
                 h = arc_hash((uint32_t)T_u[k], (uint32_t)v);
                 candidate_range(sX, sT, J, h, w, lo, hi);
             }
-            const bool act_arc = ai < A && ((cw >> (v & 31)) & 1u);
-            if (act_arc) cnt = hi - lo;
-            else lo = hi = 0;
+            cnt = hi - lo;
             if (ai < A) {
                 if (STATS && act_arc) T_act[k] = 1;
                 if (cnt > 0) T_touch[k] = 1;

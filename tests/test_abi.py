@@ -98,3 +98,11 @@ def test_set_allocator_arguments(imx):
     with pytest.raises(ValueError):
         imx.im_set_allocator(lambda n: 0, None)
     imx.im_set_allocator()  # no-op reset
+
+
+def test_profiling_levels(imx):
+    L = imx.lib()
+    for level in (1, 2, 0):
+        assert L.im_set_profiling(level) == 0
+    assert L.im_set_profiling(3) == 1  # IM_EINVAL
+    assert L.im_set_profiling(-1) == 1
