@@ -1912,18 +1912,26 @@ __global__ __launch_bounds__(kWG) void k_cascade_level(const LevelArgs* __restri
             v_nx = g.col[e0 + lane];
             w_nx = g.W[e0 + lane];
         }
+        // u's row in 16-byte chunks (4 words per lane; Jw is a multiple of
+        // 16), so a row of up to 1 KB is one load per lane
         int nE = 0;
-        for (int base = 0; base < Jw; base += 64) {
-            const int idx = base + lane;
-            uint32_t d = 0;
-            if (idx < Jw) {
-                d = Mu[idx];
-                roww[idx] = d;
+        const uint4* Mu4 = reinterpret_cast<const uint4*>(Mu);
+        for (int base = 0; base < Jw; base += 256) {
+            const int w0 = base + 4 * lane;
+            uint4 d = make_uint4(0u, 0u, 0u, 0u);
+            if (w0 < Jw) {
+                d = Mu4[w0 >> 2];
+                *reinterpret_cast<uint4*>(&roww[w0]) = d;
             }
-            const bool has = idx < Jw && eq_mask4(d, mk_prev) != 0u;
-            const unsigned long long bal = __ballot(has);
-            if (has) ED[nE + __popcll(bal & ((1ull << lane) - 1ull))] = idx;
-            nE += __popcll(bal);
+            const uint32_t hm = (eq_mask4(d.x, mk_prev) ? 1u : 0u) | (eq_mask4(d.y, mk_prev) ? 2u : 0u) |
+                                (eq_mask4(d.z, mk_prev) ? 4u : 0u) | (eq_mask4(d.w, mk_prev) ? 8u : 0u);
+            const int cnt = (w0 < Jw) ? __builtin_popcount(hm) : 0;
+            const int incl = wave_incl_scan(cnt);
+            int pos = nE + incl - cnt;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if ((hm >> k) & 1u) ED[pos++] = w0 + k;
+            nE += lane_val(incl, 63);
         }
         wave_lds_sync();
         if (nE == 0) continue;
