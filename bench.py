@@ -326,12 +326,73 @@ def served_main(args):
     print(json.dumps(out), flush=True)
 
 
+def mc_spread(g, seeds, worlds: int, rng) -> np.ndarray:
+    """Independent evaluation of an IC seed set: `worlds` live-edge graphs
+    drawn with a standard RNG (every arc live with its own probability), and
+    the number of vertices reachable from the seeds in each (BFS from a
+    super-source).  No hashing and nothing shared with the method."""
+    import numpy as np
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import breadth_first_order
+    src = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.rowptr))
+    out = np.empty(worlds, np.int64)
+    s = np.asarray(seeds, np.int64)
+    for r in range(worlds):
+        live = rng.random(g.m) < g.p
+        rows = np.concatenate([src[live], np.full(len(s), g.n)])
+        cols = np.concatenate([g.col[live].astype(np.int64), s])
+        A = sp.csr_matrix((np.ones(len(rows), np.int8), (rows, cols)), shape=(g.n + 1, g.n + 1))
+        out[r] = len(breadth_first_order(A, g.n, directed=True, return_predecessors=False)) - 1
+    return out
+
+
+def quality_main(args):
+    """Seed quality under the paper's weight settings (constant 0.005, 0.01,
+    0.1; N(0.05, 0.025); U(0, 0.1)) on an RMAT graph: the GPU's seeds and
+    sketch estimate T/J, against the spread of the same seeds by independent
+    Monte-Carlo (3 runs of `--quality-worlds` worlds, standard RNG)."""
+    import numpy as np
+
+    import graphgen
+    import torch
+
+    import paper_2410_14047_amd as imx
+    torch.cuda.set_device(0)
+    base = graphgen.rmat(args.quality_scale, 16, seed=1)
+    J, K = 1024, 50
+    rows = []
+    for scheme in ("0.005", "0.01", "0.1", "normal", "uniform01"):
+        g = graphgen.with_p(base, scheme)
+        G = imx.Graph.from_graphgen(g)
+        t = time.perf_counter()
+        S = imx.Sketch(G, J, 1)
+        r = S.select(K)
+        S.free()
+        torch.cuda.synchronize()
+        gpu_ms = (time.perf_counter() - t) * 1e3
+        G.free()
+        runs = [float(mc_spread(g, r["seeds"], args.quality_worlds, np.random.default_rng(100 + i)).mean())
+                for i in range(3)]
+        mc = float(np.mean(runs))
+        rows.append({"setting": scheme, "sketch_spread": float(r["spread"]), "mc_spread": mc,
+                     "mc_run_spreads": runs, "sketch_over_mc": float(r["spread"]) / mc, "gpu_ms": gpu_ms})
+        print(f"[bench] quality {scheme}: sketch {r['spread']:.1f} MC {mc:.1f}", file=sys.stderr, flush=True)
+    out = {"metric": "seed quality: sketch estimate vs independent Monte-Carlo spread of the same seeds",
+           "unit": "vertices", "n_gpus": 1, "data": "synthetic", "dtype": "u8",
+           "config": {"workload": f"quality_rmat{args.quality_scale}_J{J}_K{K}", "n": base.n, "m": base.m,
+                      "worlds_per_run": args.quality_worlds, "runs": 3},
+           "settings": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + ["batched64", "served"])
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + ["batched64", "served", "quality"])
+    ap.add_argument("--quality-scale", type=int, default=16, help="RMAT scale of the quality workload")
+    ap.add_argument("--quality-worlds", type=int, default=200, help="Monte-Carlo worlds per run (quality)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-roofline", action="store_true", help="skip the instrumented byte-count pass")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work in cpu_baseline")
@@ -364,6 +425,8 @@ def main():
         return batched_main(args)
     if args.workload == "served":
         return served_main(args)
+    if args.workload == "quality":
+        return quality_main(args)
     if args.gather_calibration:
         return gather_calibration(args.gather_calibration)
     if args.copy_calibration:

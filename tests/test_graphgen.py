@@ -44,3 +44,34 @@ def test_probability_schemes():
     assert set(np.unique(tri.p).tolist()) <= {np.float32(0.1), np.float32(0.01), np.float32(0.001)}
     u = graphgen.with_p(g, "0.01")
     assert np.all(u.p == np.float32(0.01))
+
+
+def test_mixed_weight_settings():
+    """N(0.05, 0.025) clipped to [0, 1] and U(0, 0.1): ranges, moments,
+    determinism for a seed."""
+    g = graphgen.rmat(12, 16, seed=3)
+    nrm = graphgen.with_p(g, "normal").p
+    assert nrm.dtype == np.float32 and nrm.min() >= 0.0 and nrm.max() <= 1.0
+    assert abs(float(nrm.mean()) - 0.05) < 0.002 and abs(float(nrm.std()) - 0.025) < 0.002
+    uni = graphgen.with_p(g, "uniform01").p
+    assert uni.min() >= 0.0 and uni.max() < 0.1
+    assert abs(float(uni.mean()) - 0.05) < 0.002
+    assert np.array_equal(graphgen.with_p(g, "normal").p, nrm)
+    assert not np.array_equal(graphgen.with_p(g, "normal", seed=9).p, nrm)
+
+
+def test_bench_monte_carlo_evaluator():
+    """The quality report's evaluator: p = 1 reaches everything reachable,
+    p = 0 only the seeds, and a path's spread under p is 1 + p + p^2 + ..."""
+    import bench
+    n = 40
+    cyc = graphgen.Graph(n=n, rowptr=np.arange(n + 1, dtype=np.int64),
+                         col=((np.arange(n) + 1) % n).astype(np.int32), p=np.ones(n, np.float32))
+    rng = np.random.default_rng(0)
+    assert np.all(bench.mc_spread(cyc, [3], 5, rng) == n)
+    cyc0 = graphgen.Graph(n=n, rowptr=cyc.rowptr, col=cyc.col, p=np.zeros(n, np.float32))
+    assert np.all(bench.mc_spread(cyc0, [3, 7], 5, rng) == 2)
+    path = graphgen.Graph(n=3, rowptr=np.array([0, 1, 2, 2], np.int64), col=np.array([1, 2], np.int32),
+                          p=np.full(2, 0.5, np.float32))
+    s = bench.mc_spread(path, [0], 4000, rng)
+    assert abs(s.mean() - 1.75) < 0.06
