@@ -156,6 +156,32 @@ im_status im_graph_load(int64_t n, int64_t m, const int64_t* rowptr_host, const 
     }
     ts[n] = (int32_t)tu.size();
     if ((int64_t)tu.size() >= (int64_t(1) << 31)) return set_error(IM_EINVAL, "too many propagation tasks");
+    // Order of a sweep that visits every task: heavy classes first (arc
+    // counts >= 64, >= 16, >= 4, the rest; task id order within a class), so
+    // the packs dealt to workgroups in turn carry similar work and the light
+    // ones fill in at the end, while most tasks keep the id order that makes
+    // their rows and arcs nearly sequential.  (A full sort by arc count
+    // balanced as well but slowed the bandwidth-bound sweeps of large
+    // uniform-probability graphs, where rows read in id order stream.)
+    std::vector<int32_t> dord(tu.size());
+    {
+        auto cls = [&](size_t t) {
+            const uint32_t l = tl[t] & 0x7fffffffu;
+            return l >= 64 ? 0 : l >= 16 ? 1 : l >= 4 ? 2 : 3;
+        };
+        int64_t cnt[5] = {0, 0, 0, 0, 0};
+        for (size_t t = 0; t < tl.size(); ++t) ++cnt[cls(t) + 1];
+        for (int i = 1; i < 5; ++i) cnt[i] += cnt[i - 1];
+        for (size_t t = 0; t < tl.size(); ++t) dord[(size_t)cnt[cls(t)]++] = (int32_t)t;
+    }
+    std::vector<int32_t> du(dord.size());
+    std::vector<int64_t> de(dord.size());
+    std::vector<uint32_t> dl(dord.size());
+    for (size_t i = 0; i < dord.size(); ++i) {
+        du[i] = tu[(size_t)dord[i]];
+        de[i] = te[(size_t)dord[i]];
+        dl[i] = tl[(size_t)dord[i]];
+    }
     // reverse graph: in-arcs of every vertex, sources ascending
     std::vector<int64_t> irp(n + 1, 0);
     for (int64_t e = 0; e < m; ++e) ++irp[col_host[e] + 1];
@@ -177,7 +203,7 @@ im_status im_graph_load(int64_t n, int64_t m, const int64_t* rowptr_host, const 
     }
     its[n] = (int32_t)itv.size();
 
-    size_t need = sizeof(int64_t) * (n + 1) * 2 + (size_t)m * 16 + tu.size() * 12 + itv.size() * 12 + (size_t)n * 8;
+    size_t need = sizeof(int64_t) * (n + 1) * 2 + (size_t)m * 16 + tu.size() * 32 + itv.size() * 12 + (size_t)n * 8;
     size_t free_b = 0, total_b = 0;
     IMX_HIP(hipMemGetInfo(&free_b, &total_b));
     if (need + (64u << 20) > free_b) return set_error(IM_ENOMEM, "graph does not fit in device memory");
@@ -202,7 +228,8 @@ im_status im_graph_load(int64_t n, int64_t m, const int64_t* rowptr_host, const 
     if (A.alloc(&g->rowptr, n + 1) || A.alloc(&g->col, m) || A.alloc(&g->W, m) || A.alloc(&g->task_u, tu.size()) ||
         A.alloc(&g->task_e0, te.size()) || A.alloc(&g->task_len, tl.size()) || A.alloc(&g->task_start, n + 1) || A.alloc(&g->in_rowptr, n + 1) ||
         A.alloc(&g->in_col, m) || A.alloc(&g->in_task_v, itv.size()) || A.alloc(&g->in_task_e0, ite.size()) ||
-        A.alloc(&g->in_task_start, n + 1) || tmp.alloc(&p_dev, (size_t)m))
+        A.alloc(&g->in_task_start, n + 1) || A.alloc(&g->dense_u, du.size()) || A.alloc(&g->dense_e0, de.size()) ||
+        A.alloc(&g->dense_len, dl.size()) || tmp.alloc(&p_dev, (size_t)m))
         return cleanup(IM_ENOMEM, "device allocation failed");
     hipStream_t st = g->stream;
     hipError_t e = hipMemcpyAsync(g->rowptr, rowptr_host, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, st);
@@ -214,6 +241,12 @@ im_status im_graph_load(int64_t n, int64_t m, const int64_t* rowptr_host, const 
         e = hipMemcpyAsync(g->task_e0, te.data(), sizeof(int64_t) * te.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess && !tl.empty())
         e = hipMemcpyAsync(g->task_len, tl.data(), sizeof(uint32_t) * tl.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !du.empty())
+        e = hipMemcpyAsync(g->dense_u, du.data(), sizeof(int32_t) * du.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !de.empty())
+        e = hipMemcpyAsync(g->dense_e0, de.data(), sizeof(int64_t) * de.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !dl.empty())
+        e = hipMemcpyAsync(g->dense_len, dl.data(), sizeof(uint32_t) * dl.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(g->task_start, ts.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, st);
     if (e == hipSuccess)

@@ -90,12 +90,16 @@ struct im_graph {
     int32_t* in_task_start = nullptr;
     int64_t n_in_tasks = 0;
     int32_t in_split = 256;
+    int32_t* dense_u = nullptr;
+    int64_t* dense_e0 = nullptr;
+    uint32_t* dense_len = nullptr;
     imx::Arena arena;
 
     imx::GraphDev dev() const
     {
         return imx::GraphDev{n,          m,         rowptr,     col,           W,          task_u,
                              task_e0,    task_len,  task_start, ntasks,        split,      in_rowptr,
-                             in_col,     in_task_v, in_task_e0, in_task_start, n_in_tasks, in_split};
+                             in_col,     in_task_v, in_task_e0, in_task_start, n_in_tasks, in_split,
+                             dense_u,    dense_e0,  dense_len};
     }
 };

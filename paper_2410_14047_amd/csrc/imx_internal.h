@@ -64,6 +64,11 @@ struct GraphDevT {
     dptr<const int32_t, G> in_task_start; // [n+1]
     int64_t n_in_tasks;
     int32_t in_split;
+    // The task records again, ordered by descending arc count (ties by task
+    // id): the order in which a sweep that visits every task deals them.
+    dptr<const int32_t, G> dense_u;      // [ntasks]
+    dptr<const int64_t, G> dense_e0;     // [ntasks]
+    dptr<const uint32_t, G> dense_len;   // [ntasks]
 };
 using GraphDev = GraphDevT<false>;
 

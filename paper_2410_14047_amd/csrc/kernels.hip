@@ -1094,6 +1094,10 @@ __global__ __launch_bounds__(kPackWG, 3) void k_propagate_pack(const PropArgs* _
         const int64_t q = pk * P + lane;
         return (lane < P && pk < npacks && q < count) ? (tasks ? tasks[q] : (int32_t)q) : -1;
     };
+    // task records: by task id from a list, or by position in the dense order
+    const auto rec_u = tasks ? g.task_u : g.dense_u;
+    const auto rec_e0 = tasks ? g.task_e0 : g.dense_e0;
+    const auto rec_len = tasks ? g.task_len : g.dense_len;
     // Draw k of a workgroup is pack lb + k * lg (workgroups interleaved over
     // the list).  A wave's first two draws are fixed (k = wave, wave + 8);
     // later ones come from the workgroup's LDS counter, so the waves of a
@@ -1115,9 +1119,9 @@ __global__ __launch_bounds__(kPackWG, 3) void k_propagate_pack(const PropArgs* _
     int64_t e0_nx = 0;
     uint32_t len_nx = 0;
     if (t_nx >= 0) {
-        u_nx = g.task_u[t_nx];
-        e0_nx = g.task_e0[t_nx];
-        len_nx = g.task_len[t_nx];
+        u_nx = rec_u[t_nx];
+        e0_nx = rec_e0[t_nx];
+        len_nx = rec_len[t_nx];
     }
     int32_t t_nx2 = task_id(pk_n1);
     for (; pk < npacks; pk = pk_n1, pk_n1 = pk_n2) {
@@ -1132,9 +1136,9 @@ __global__ __launch_bounds__(kPackWG, 3) void k_propagate_pack(const PropArgs* _
         // next pack's records, and the ids of the one after
         t_nx = t_nx2;
         if (t_nx >= 0) {
-            u_nx = g.task_u[t_nx];
-            e0_nx = g.task_e0[t_nx];
-            len_nx = g.task_len[t_nx];
+            u_nx = rec_u[t_nx];
+            e0_nx = rec_e0[t_nx];
+            len_nx = rec_len[t_nx];
         }
         pk_n2 = pack_of(lane_val(drawn, 0));
         drawn = (pk_n2 < npacks) ? draw() : ~0u;  // wave-uniform
