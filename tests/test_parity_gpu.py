@@ -80,6 +80,7 @@ CASES = {
     "er60_p1_J128_Kn": (lambda: graphgen.with_p(graphgen.erdos_renyi(60, 150, 8), "1.0"), 128, 15, 60),
     "er400_normal_J128": (lambda: graphgen.with_p(graphgen.erdos_renyi(400, 4000, 9), "normal"), 128, 16, 8),
     "rmat11_uniform01_J256": (lambda: graphgen.with_p(graphgen.rmat(11, 16, seed=4), "uniform01"), 256, 17, 6),
+    "rmat11_p0.005_J1024": (lambda: graphgen.with_p(graphgen.rmat(11, 16, seed=6), "0.005"), 1024, 18, 6),
 }
 
 
