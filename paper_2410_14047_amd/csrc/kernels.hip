@@ -1898,17 +1898,32 @@ __global__ __launch_bounds__(kWG) void k_cascade_level(const LevelArgs* __restri
     const uint32_t* M32 = reinterpret_cast<const uint32_t*>(a.M);
     const int64_t nw = lg * kWaves;
 
-    // The next task's id is loaded one task ahead; the first chunk of arcs is
-    // loaded with u's row, and every later chunk while the previous one is
-    // processed.
+    // Task records are loaded one task ahead and task ids two ahead; the
+    // first chunk of arcs is loaded with u's row, and every later chunk while
+    // the previous one is processed.
     int64_t i = lb * kWaves + wave;
-    int32_t t_next = (i < (int64_t)qn) ? Q[i] : 0;
+    int32_t t_nx = (i < (int64_t)qn) ? Q[i] : -1;
+    int32_t u_nx = 0;
+    int64_t e0_nx = 0;
+    uint32_t len_nx = 0;
+    if (t_nx >= 0) {
+        u_nx = g.task_u[t_nx];
+        e0_nx = g.task_e0[t_nx];
+        len_nx = g.task_len[t_nx];
+    }
+    int32_t t_nx2 = (i + nw < (int64_t)qn) ? Q[i + nw] : -1;
     for (; i < (int64_t)qn; i += nw) {
-        const int32_t t = t_next;
-        if (i + nw < (int64_t)qn) t_next = Q[i + nw];
-        const int32_t u = g.task_u[t];
-        const int64_t e0 = g.task_e0[t];
-        const int64_t e1 = e0 + (int64_t)(g.task_len[t] & 0x7fffffffu);
+        const int32_t u = u_nx;
+        const int64_t e0 = e0_nx;
+        const int64_t e1 = e0 + (int64_t)(len_nx & 0x7fffffffu);
+        // the next task's records, and the id of the one after
+        t_nx = t_nx2;
+        if (t_nx >= 0) {
+            u_nx = g.task_u[t_nx];
+            e0_nx = g.task_e0[t_nx];
+            len_nx = g.task_len[t_nx];
+        }
+        t_nx2 = (i + 2 * nw < (int64_t)qn) ? Q[i + 2 * nw] : -1;
         const uint32_t* Mu = M32 + (size_t)u * (size_t)Jw;
         int32_t v_nx = 0;
         uint32_t w_nx = 0;
