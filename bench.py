@@ -100,7 +100,7 @@ def pmc_summary(args):
         raise SystemExit("no k_propagate dispatches in the counter files")
     fb = float(np.mean(fr)) * 1024 * f_fetch
     wb = float(np.mean(wr)) * 1024 * f_write
-    d = {"workload": args.workload, "kernel": "k_propagate", "kernel_source_hash": kernel_source_hash(),
+    d = {"workload": args.workload, "kernel": "k_propagate_pack", "kernel_source_hash": kernel_source_hash(),
          "dispatches": [len(fr), len(wr)], "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
          "hbm_bytes_per_launch": fb + wb, "copy_calibration": {"bytes": copy_bytes, "fetch_factor": f_fetch,
                                                                "write_factor": f_write},
@@ -524,7 +524,7 @@ def main():
         traffic = pmc_traffic(args.workload, bpl)
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                           "kernel": "k_propagate", "alg_bytes_per_launch": bpl,
+                           "kernel": "k_propagate_pack", "alg_bytes_per_launch": bpl,
                            "avg_launch_us": tpl * 1e6,
                            "per_launch": {k: st[k] / st["prop_launches"] for k in
                                           ("prop_rows_visited", "prop_rows_changed", "prop_arcs_active",
