@@ -65,7 +65,7 @@ def lib():
         L.orc_fill.restype = None
         L.orc_build.argtypes = [i64, P, P, P, i32, u64, P, P]
         L.orc_build.restype = ctypes.c_int
-        L.orc_sweeps_sample.argtypes = [i64, P, P, P, i32, u64, P, i32, i32, P]
+        L.orc_sweeps_sample.argtypes = [i64, P, P, P, i32, u64, P, i32, i32, P, P]
         L.orc_sweeps_sample.restype = ctypes.c_int
         L.orc_estimates.argtypes = [i64, i32, P, P, P, P]
         L.orc_estimates.restype = None
@@ -153,15 +153,19 @@ def build(g, J: int, seed: int):
     return M, int(sw[0])
 
 
-def sweeps_sample(g, J: int, seed: int, sims, nsweeps: int) -> int:
+def sweeps_sample(g, J: int, seed: int, sims, nsweeps: int, registers: bool = False):
+    """`nsweeps` synchronous sweeps (Alg. 2) from Fill (Alg. 1) over the
+    simulation columns `sims` only.  Returns the number of registers the last
+    sweep changed, and with registers=True also the registers uint8[n, len(sims)]."""
     rowptr, col, p = _graph_arrays(g)
     sims = np.ascontiguousarray(sims, dtype=np.int32)
     ch = np.zeros(1, dtype=np.int64)
+    M = np.zeros((g.n, len(sims)), dtype=np.uint8) if registers else None
     st = lib().orc_sweeps_sample(g.n, _ptr(rowptr), _ptr(col), _ptr(p), J, seed & (2**64 - 1),
-                                 _ptr(sims), len(sims), nsweeps, _ptr(ch))
+                                 _ptr(sims), len(sims), nsweeps, _ptr(ch), _ptr(M))
     if st:
         raise RuntimeError(f"orc_sweeps_sample failed: {st}")
-    return int(ch[0])
+    return (int(ch[0]), M) if registers else int(ch[0])
 
 
 def estimates(M: np.ndarray, cov: Optional[np.ndarray] = None):

@@ -258,12 +258,15 @@ int orc_build(int64_t n, const int64_t* rowptr, const int32_t* col, const float*
     return ORC_OK;
 }
 
-/* Run `nsweeps` synchronous sweeps for a subset of simulations only (columns
- * sims[0..S-1] of a J-wide sketch) starting from Fill; used to time the oracle
- * on a bounded sample of a large workload.  Returns changed-register counts of
- * the last sweep in *last_changed. */
+/* Run `nsweeps` synchronous sweeps of Alg. 2 for a subset of simulations only
+ * (columns sims[0..S-1] of a J-wide sketch, nothing covered) starting from
+ * Fill (Alg. 1); used to time the oracle on a bounded sample of a large
+ * workload.  Returns the number of registers the last sweep changed in
+ * *last_changed and, when M_out is not NULL, the registers after the last
+ * sweep as uint8[n][S] (column s is simulation sims[s]). */
 int orc_sweeps_sample(int64_t n, const int64_t* rowptr, const int32_t* col, const float* p, int32_t J,
-                      uint64_t seed, const int32_t* sims, int32_t S, int32_t nsweeps, int64_t* last_changed)
+                      uint64_t seed, const int32_t* sims, int32_t S, int32_t nsweeps, int64_t* last_changed,
+                      uint8_t* M_out)
 {
     orc_graph g;
     int st = graph_init(&g, n, rowptr, col, p);
@@ -283,6 +286,7 @@ int orc_sweeps_sample(int64_t n, const int64_t* rowptr, const int32_t* col, cons
         memcpy(M, Mn, (size_t)n * (size_t)S);
     }
     if (last_changed) *last_changed = ch;
+    if (M_out) memcpy(M_out, M, (size_t)n * (size_t)S);
     free(X); free(Xs); free(M); free(Mn); graph_free(&g);
     return ORC_OK;
 }

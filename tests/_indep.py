@@ -54,6 +54,20 @@ def live_digraphs(g, X):
     return out
 
 
+def hop_limited_registers(g, X, seed, sims, hops):
+    """Registers after `hops` synchronous sweeps from the fill, nothing covered:
+    register (u, j) is the max rank over the vertices within `hops` live arcs
+    of u in simulation j (a sweep extends every register by one arc).  Returns
+    uint8[n, len(sims)], column s for simulation sims[s]."""
+    graphs = live_digraphs(g, [X[j] for j in sims])
+    M = np.zeros((g.n, len(sims)), dtype=np.uint8)
+    for s, (j, G) in enumerate(zip(sims, graphs)):
+        for u in range(g.n):
+            near = nx.single_source_shortest_path_length(G, u, cutoff=hops)
+            M[u, s] = max(sk_rank(seed, w, int(j)) for w in near)
+    return M
+
+
 def closed_form_registers(g, X, seed, covered=None):
     """Registers at the fixed point: for uncovered (u, j), the max rank over the
     vertices reachable from u in the live graph of j through uncovered vertices."""

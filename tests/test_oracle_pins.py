@@ -216,6 +216,69 @@ def test_fixed_point_invariants(orc):
         assert M[u, j] == lg.reach_max(int(X[j]), seed, j, u)
 
 
+@settings(max_examples=20, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(n=st.integers(1, 60), dens=st.floats(0.0, 3.0), gseed=st.integers(0, 10**6),
+       sseed=st.integers(0, 2**64 - 1), data=st.data())
+def test_cover_from_is_union_of_reachability_sets(orc, n, dens, gseed, sseed, data):
+    """The covered-set checker (the result of Alg. 3 for a seed set) equals
+    the union of the seeds' descendants in each simulation's live graph."""
+    g = _random_graph(n, int(dens * n), gseed, [0.05, 0.3, 0.7, 1.0])
+    X = orc.sim_values(sseed, 64)
+    lg = orc.LiveGraph(g)
+    js = data.draw(st.lists(st.integers(0, 63), min_size=1, max_size=4, unique=True))
+    seeds = data.draw(st.lists(st.integers(0, n - 1), min_size=1, max_size=6))
+    for j, G in zip(js, _indep.live_digraphs(g, [X[j] for j in js])):
+        expect = np.zeros(n, np.uint8)
+        for s in seeds:
+            expect[list(nx.descendants(G, s) | {s})] = 1
+        assert np.array_equal(lg.cover_from(int(X[j]), seeds), expect), j
+
+
+@pytest.mark.parametrize("gseed,p", [(31, [0.05, 0.3, 0.7, 1.0]), (32, [0.5]), (33, [1.0])])
+def test_reach_max_equals_closed_form_every_pair(orc, gseed, p):
+    """The single-register checker equals the closed form of the fixed point
+    for every (u, j): without covered sets, with arbitrary covered sets, and
+    with the covered sets a cascade leaves (closed under live arcs)."""
+    g = _random_graph(26, 70, gseed, p)
+    J, seed = 64, 1000 + gseed
+    X = orc.sim_values(seed, J)
+    lg = orc.LiveGraph(g)
+    rng = np.random.default_rng(gseed)
+    free = _indep.closed_form_registers(g, X, seed)
+    arbitrary = (rng.random((g.n, J)) < 0.25).astype(np.uint8)
+    cascade = _bfs_cover(g, X, [int(x) for x in rng.choice(g.n, 2, replace=False)])
+    for cov in (None, arbitrary, cascade):
+        expect = free if cov is None else _indep.closed_form_registers(g, X, seed, covered=cov)
+        if cov is not None:
+            expect[cov == 1] = 0
+        for j in range(J):
+            cj = None if cov is None else cov[:, j]
+            got = [lg.reach_max(int(X[j]), seed, j, u, cj) for u in range(g.n)]
+            assert got == expect[:, j].tolist(), j
+
+
+@pytest.mark.parametrize("hops", [0, 1, 2, 3, 40])
+def test_sweeps_sample_is_hop_limited_reachability(orc, hops):
+    """After s synchronous sweeps from the fill, each sampled column holds the
+    max rank within s live arcs (Alg. 2 extends every register by one arc per
+    sweep); the last sweep's change count is the number of registers that
+    differ between s - 1 and s arcs."""
+    g = _random_graph(40, 110, 41, [0.1, 0.4, 0.8, 1.0])
+    J, seed = 128, 77
+    sims = [5, 0, 127, 64, 17]
+    X = orc.sim_values(seed, J)
+    ch, M = orc.sweeps_sample(g, J, seed, sims, hops, registers=True)
+    expect = _indep.hop_limited_registers(g, X, seed, sims, hops)
+    assert np.array_equal(M, expect)
+    if hops == 0:
+        assert ch == 0
+    else:
+        prev = _indep.hop_limited_registers(g, X, seed, sims, hops - 1)
+        assert ch == int(np.count_nonzero(prev != expect))
+    if hops == 40:  # past the longest shortest path: the fixed point's columns
+        assert np.array_equal(M, _indep.closed_form_registers(g, X, seed)[:, sims])
+
+
 # ---------------------------------------------------------------- estimate and argmax (Eq. 7)
 
 def test_hll_alpha_constants(orc):
