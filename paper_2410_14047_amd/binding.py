@@ -68,7 +68,11 @@ _lib = None
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
-_hooks = None  # keeps the active ctypes callbacks alive
+# Every hook pair ever installed stays referenced for the life of the process:
+# a buffer is returned to the hooks that allocated it (also after the hooks
+# change), so a ctypes thunk must never be collected while such a buffer may
+# still be freed.
+_hooks_installed: list = []
 
 
 def lib() -> ctypes.CDLL:
@@ -169,12 +173,10 @@ def im_set_profiling(level: int) -> None:
 def im_set_allocator(alloc=None, free=None) -> None:
     """Install device memory hooks: alloc(nbytes) -> int device pointer (0 on
     failure), free(ptr) -> None.  Both None restores hipMalloc/hipFree."""
-    global _hooks
     if (alloc is None) != (free is None):
         raise ValueError("give both hooks or neither")
     if alloc is None:
         _check(lib().im_set_allocator(_ALLOC_FN(), _FREE_FN(), None))
-        _hooks = None
         return
 
     def _a(nbytes, ctx):
@@ -190,8 +192,8 @@ def im_set_allocator(alloc=None, free=None) -> None:
             pass
 
     hooks = (_ALLOC_FN(_a), _FREE_FN(_f))
+    _hooks_installed.append(hooks)
     _check(lib().im_set_allocator(hooks[0], hooks[1], None))
-    _hooks = hooks
 
 
 def use_torch_allocator(enable: bool = True, device: int = 0) -> None:

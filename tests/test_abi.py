@@ -106,3 +106,24 @@ def test_profiling_levels(imx):
         assert L.im_set_profiling(level) == 0
     assert L.im_set_profiling(3) == 1  # IM_EINVAL
     assert L.im_set_profiling(-1) == 1
+
+
+def test_allocator_hooks_outlive_reinstallation(imx):
+    """A buffer is returned to the hooks that allocated it, even after other
+    hooks were installed or the default restored; the ctypes thunks of every
+    installed pair must therefore stay valid for the life of the process."""
+    import gc
+
+    from paper_2410_14047_amd import binding
+    freed = []
+    binding.im_set_allocator(lambda n: 0, lambda p: freed.append(p))
+    first = binding._hooks_installed[-1]
+    binding.im_set_allocator(lambda n: 0, lambda p: None)
+    binding.im_set_allocator()  # back to hipMalloc / hipFree
+    gc.collect()
+    assert any(h is first for h in binding._hooks_installed)
+    # the first pair's free thunk, called through its C function pointer as the
+    # library would when a block it allocated is released, still reaches Python
+    fptr = ctypes.cast(first[1], ctypes.c_void_p).value
+    ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)(fptr)(ctypes.c_void_p(0x1234), None)
+    assert freed == [0x1234]
