@@ -39,7 +39,10 @@ WORKLOADS = {
     "rmat24_tri_J1024_K50": dict(kind="rmat", scale=24, ef=16, scheme="trivalency", J=1024, K=50, gseed=1,
                                  sseed=1),
 }
-DEFAULT = "rmat20_wc_J512_K50"
+DEFAULT = "rmat24_p0.01_J1024_K50"
+# Workloads measured beside the default in the same run (same topology, another
+# probability scheme), reported in the line's `variants` field.
+VARIANTS = {"rmat24_p0.01_J1024_K50": ["rmat24_tri_J1024_K50"]}
 
 
 def make_graph(w):
@@ -395,6 +398,8 @@ def main():
     ap.add_argument("--quality-worlds", type=int, default=200, help="Monte-Carlo worlds per run (quality)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-roofline", action="store_true", help="skip the instrumented byte-count pass")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="measure only the named workload (not the variants reported beside it)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work in cpu_baseline")
     ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1),
                     help="host threads of the cpu_baseline oracle run (default: all cores, at most 16)")
@@ -442,6 +447,7 @@ def main():
 
     import torch
 
+    import graphgen
     import paper_2410_14047_amd as imx
 
     w = WORKLOADS[args.workload]
@@ -451,6 +457,44 @@ def main():
           file=sys.stderr, flush=True)
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    out = {
+        "metric": METRIC,
+        "value": None,
+        "unit": "register updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+    }
+    main_res = measure(imx, g, w, args.workload, args.steps, args.warmup, not args.no_roofline, stream)
+    out.update(main_res)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(g, w, args.cpu_budget, args.cpu_threads)
+    if not args.no_variants and VARIANTS.get(args.workload):
+        out["variants"] = {}
+        for name in VARIANTS[args.workload]:
+            wv = WORKLOADS[name]
+            gv = graphgen.with_p(g, wv["scheme"])  # same topology, another probability scheme
+            res = measure(imx, gv, wv, name, max(1, args.steps // 2 + 1), args.warmup, not args.no_roofline, stream)
+            out["variants"][name] = {k: res[k] for k in ("value", "unit", "ms_per_step", "config", "k_seed_wall_ms_median",
+                                                         "sweeps_per_step", "rebuilds_per_step", "spread",
+                                                         "propagate_kernel_ms_per_step", "roofline") if k in res}
+            out["variants"][name]["unit"] = "register updates/s"
+            out["variants"][name]["steps"] = max(1, args.steps // 2 + 1)
+            del gv
+    print(json.dumps(out), flush=True)
+
+
+def measure(imx, g, w, workload, steps, warmup, roofline, stream):
+    """Load the graph, run `warmup` untimed and `steps` timed build + select
+    steps and (optionally) the instrumented pass for the roofline; returns the
+    fields of the bench line for this workload."""
+    import torch
     torch.cuda.synchronize()
     t_load = time.perf_counter()
     G = imx.Graph.from_graphgen(g, stream=stream)
@@ -468,15 +512,15 @@ def main():
         step_ms.append((time.perf_counter() - t) * 1e3)
         return r
 
-    for i in range(args.warmup):
+    for i in range(warmup):
         r = step()
-        print(f"[bench] warmup {i}: {r['stats']['select_ms'] + r['stats']['build_ms']:.1f} ms", file=sys.stderr,
-              flush=True)
+        print(f"[bench] {workload} warmup {i}: {r['stats']['select_ms'] + r['stats']['build_ms']:.1f} ms",
+              file=sys.stderr, flush=True)
 
     torch.cuda.synchronize()
     step_ms.clear()
     t_start = time.perf_counter()
-    results = [step() for _ in range(args.steps)]
+    results = [step() for _ in range(steps)]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     for r in results[1:]:
@@ -485,58 +529,48 @@ def main():
     sweeps = sum(r["stats"]["total_sweeps"] for r in results)
     launches = sum(r["stats"]["prop_launches"] for r in results)
     kms = sum(r["stats"]["prop_kernel_ms"] for r in results)
-    value = J * g.m * sweeps / wall
     out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "register updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u8",
-        "data": "synthetic",
-        "config": {"workload": args.workload, "n": g.n, "m": g.m, "J": J, "K": K, "p_scheme": w["scheme"],
+        "value": J * g.m * sweeps / wall,
+        "ms_per_step": wall / steps * 1e3,
+        "config": {"workload": workload, "n": g.n, "m": g.m, "J": J, "K": K, "p_scheme": w["scheme"],
                    "graph_seed": w["gseed"], "sketch_seed": seed, "parallelism": "single GPU"},
-        "k_seed_wall_ms": wall / args.steps * 1e3,
+        "k_seed_wall_ms": wall / steps * 1e3,
         "k_seed_wall_ms_median": float(sorted(step_ms)[len(step_ms) // 2]),
         "graph_load_ms": load_ms,
-        "sweeps_per_step": sweeps / args.steps,
+        "sweeps_per_step": sweeps / steps,
         "rebuilds_per_step": results[0]["stats"]["rebuilds"],
         "spread": results[0]["spread"],
-        "propagate_kernel_ms_per_step": kms / args.steps,
+        "propagate_kernel_ms_per_step": kms / steps,
         "propagate_launch_avg_us": kms / launches * 1e3,
     }
+    print(f"[bench] {workload}: {out['ms_per_step']:.1f} ms/step, {out['value']:.3e} updates/s",
+          file=sys.stderr, flush=True)
 
-    if not args.no_roofline:
+    if roofline:
         imx.im_set_profiling(2)
         S = imx.Sketch(G, J, seed, stream=stream)
         rr = S.select(K)
         S.free()
+        imx.im_set_profiling(1)
         st = rr["stats"]
         assert list(rr["seeds"]) == list(results[0]["seeds"]), "instrumented run disagrees"
         bpl = st["prop_alg_bytes"] / st["prop_launches"]
         tpl = kms / launches * 1e-3
         achieved = bpl / tpl / 1e9
-        traffic = pmc_traffic(args.workload, bpl)
+        traffic = pmc_traffic(workload, bpl)
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                            "kernel": "k_propagate_pack", "alg_bytes_per_launch": bpl,
                            "avg_launch_us": tpl * 1e6,
+                           "traffic_over_algorithmic": (traffic / bpl) if traffic else None,
                            "per_launch": {k: st[k] / st["prop_launches"] for k in
                                           ("prop_rows_visited", "prop_rows_changed", "prop_arcs_active",
                                            "prop_sectors", "prop_tasks", "prop_rows_read", "prop_bytes_written",
                                            "prop_arcs_scanned")}}
-        print(f"[bench] roofline: {bpl / 1e6:.1f} MB/launch, {tpl * 1e6:.1f} us/launch, {achieved:.0f} GB/s",
-              file=sys.stderr, flush=True)
-
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(g, w, args.cpu_budget, args.cpu_threads)
+        print(f"[bench] {workload} roofline: {bpl / 1e6:.1f} MB/launch, {tpl * 1e6:.1f} us/launch, "
+              f"{achieved:.0f} GB/s", file=sys.stderr, flush=True)
     G.free()
-    print(json.dumps(out), flush=True)
+    return out
 
 
 if __name__ == "__main__":

@@ -179,6 +179,27 @@ im_status im_sketch_build(const im_graph* g, int32_t J, uint64_t seed, void* str
 im_status im_select_seeds(im_sketch* s, int32_t K, int32_t* seeds_host, double* spread_out, double* est_host,
                           uint64_t* T_host, im_stats* stats_out);
 
+/*
+ * Parity hook: run the greedy loop of im_select_seeds(s, K, ...) only up to
+ * pick number k_stop (0-based) and pause before it, so a test can compare the
+ * state every pick reads (Alg. 4 loop: estimate terms, registers after each
+ * rebuild, covered registers) with a reference.  At the pause the registers
+ * (im_sketch_registers / im_sketch_register_rows) are those pick k_stop
+ * reads, after every cascade so far and any rebuild, and the estimate terms
+ * (im_sketch_estimates) are current.  A later call with a larger k_stop goes
+ * on; im_select_seeds(s, K, ...) with the same K finishes the loop and
+ * returns every output as if it had run uninterrupted (results never depend
+ * on pauses).
+ *   K           as for im_select_seeds; the same K on every call of one sketch.
+ *   k_stop      picks to make before pausing, in [0, K) and not below the
+ *               picks already made.
+ *   seeds_host  optional int32[k_stop]: the picks made so far.
+ *   T_host      optional uint64[k_stop]: T after each of their cascades.
+ * Errors: IM_EINVAL (K or k_stop out of range, K differing from the paused
+ * selection's), IM_ESTATE (selection finished), IM_EDEVICE.
+ */
+im_status im_select_seeds_until(im_sketch* s, int32_t K, int32_t k_stop, int32_t* seeds_host, uint64_t* T_host);
+
 /* Copy the current registers to host memory uint8[n*J] (vertex-major; covered
  * registers read 0, uncovered ones hold rank values 1..33).  Parity hook. */
 im_status im_sketch_registers(const im_sketch* s, uint8_t* regs_host);

@@ -56,7 +56,7 @@ class im_stats(ctypes.Structure):
 # Every symbol declared in include/im.h.
 EXPORTS = [
     "im_last_error", "im_version", "im_set_profiling", "im_graph_load", "im_graph_info", "im_graph_free",
-    "im_sketch_build", "im_select_seeds", "im_sketch_registers", "im_sketch_register_rows", "im_sketch_estimates",
+    "im_sketch_build", "im_select_seeds", "im_select_seeds_until", "im_sketch_registers", "im_sketch_register_rows", "im_sketch_estimates",
     "im_sketch_stats", "im_sketch_sim_values", "im_sketch_free",
     "im_engine_create", "im_engine_submit", "im_engine_step", "im_engine_poll", "im_engine_result",
     "im_engine_info", "im_query_footprint", "im_engine_free", "im_select_seeds_batch",
@@ -106,6 +106,7 @@ def lib() -> ctypes.CDLL:
         L.im_graph_free.restype = None
         L.im_sketch_build.argtypes = [P, i32, u64, P, P]
         L.im_select_seeds.argtypes = [P, i32, P, P, P, P, P]
+        L.im_select_seeds_until.argtypes = [P, i32, i32, P, P]
         L.im_sketch_registers.argtypes = [P, P]
         L.im_sketch_register_rows.argtypes = [P, P, i32, P]
         L.im_sketch_estimates.argtypes = [P, P, P]
@@ -233,6 +234,14 @@ def im_select_seeds(s, K: int):
     return dict(seeds=seeds, spread=spread.value, est=est, T=T, stats=stats.as_dict())
 
 
+def im_select_seeds_until(s, K: int, k_stop: int):
+    """Picks before pick number k_stop (parity hook); returns (seeds, T) so far."""
+    seeds = np.zeros(max(k_stop, 1), dtype=np.int32)
+    T = np.zeros(max(k_stop, 1), dtype=np.uint64)
+    _check(lib().im_select_seeds_until(s, K, k_stop, _p(seeds), _p(T)))
+    return seeds[:k_stop], T[:k_stop]
+
+
 def im_sketch_registers(s, n: int, J: int) -> np.ndarray:
     M = np.zeros((n, J), dtype=np.uint8)
     _check(lib().im_sketch_registers(s, _p(M)))
@@ -306,6 +315,11 @@ class Sketch:
 
     def select(self, K: int) -> dict:
         return im_select_seeds(self.handle, K)
+
+    def select_until(self, K: int, k_stop: int):
+        """Run the selection of K seeds up to pick k_stop and pause there
+        (parity hook); select(K) finishes it.  Returns (seeds, T) so far."""
+        return im_select_seeds_until(self.handle, K, k_stop)
 
     def registers(self) -> np.ndarray:
         return im_sketch_registers(self.handle, self.graph.n, self.J)

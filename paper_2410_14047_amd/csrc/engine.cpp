@@ -39,7 +39,9 @@ struct SlotStatus {
 };
 static_assert(sizeof(SlotStatus) == 128, "status record size");
 
-enum class Stage { Fill, Sweeps, Estimate, Pick, Levels, Built, Done, Failed };
+// Paused: stopped before pick `pause_k` with current registers and estimate
+// terms (the parity hook im_select_seeds_until).
+enum class Stage { Fill, Sweeps, Estimate, Pick, Levels, Built, Paused, Done, Failed };
 
 double now_ms()
 {
@@ -57,6 +59,7 @@ struct Query {
     uint64_t seed = 0;
     int K = 0;
     bool park = false;  // stop after the initial build (sketch API)
+    int pause_k = -1;   // stop before pick number pause_k (>= 0), parity hook
     Arena arena;
     uint8_t* M = nullptr;
     uint32_t* X = nullptr;
@@ -154,7 +157,9 @@ public:
     {
         int a = 0;
         for (Query* q : slots_)
-            if (q && q->stage != Stage::Done && q->stage != Stage::Built && q->stage != Stage::Failed) ++a;
+            if (q && q->stage != Stage::Done && q->stage != Stage::Built && q->stage != Stage::Paused &&
+                q->stage != Stage::Failed)
+                ++a;
         return a;
     }
 
@@ -257,18 +262,51 @@ public:
         return IM_OK;
     }
 
-    // A parked (built) query starts selecting K seeds.
-    im_status resume(Query* q, int K)
+    // A parked (built) query starts selecting K seeds, or a paused one goes on;
+    // it stops again before pick `pause_k` (-1: runs to the end).
+    im_status resume(Query* q, int K, int pause_k)
     {
+        if (q->stage == Stage::Paused) {
+            if (K != q->K) return set_error(IM_EINVAL, "K differs from the K of the paused selection");
+            if (pause_k >= 0 && (pause_k < q->k || pause_k >= K))
+                return set_error(IM_EINVAL, "pause pick must lie in [picks made, K)");
+            q->pause_k = pause_k;
+            enter_pick(q);
+            return IM_OK;
+        }
         if (q->stage != Stage::Built) return set_error(IM_ESTATE, "seeds were already selected on this sketch");
         if (K < 1 || K > q->g->n) return set_error(IM_EINVAL, "K must be in [1, n]");
+        if (pause_k >= K) return set_error(IM_EINVAL, "pause pick must lie in [0, K)");
         const size_t before = q->arena.bytes;
         if (alloc_results(q, K) != IM_OK) return IM_ENOMEM;
         used_ += q->arena.bytes - before;
         q->K = K;
         q->park = false;
-        q->stage = Stage::Pick;
+        q->pause_k = pause_k;
         q->t_sel0 = now_ms();
+        enter_pick(q);
+        return IM_OK;
+    }
+
+    // Next stage of a query whose next step is a pick: the pick itself, or a
+    // pause before it (estimate terms first when a build just finished).
+    static void enter_pick(Query* q)
+    {
+        if (q->pause_k >= 0 && q->k >= q->pause_k)
+            q->stage = q->need_est ? Stage::Estimate : Stage::Paused;
+        else
+            q->stage = Stage::Pick;
+    }
+
+    // Seeds picked so far and T after each of their cascades.
+    im_status partial_results(Query* q, int32_t* seeds, uint64_t* T)
+    {
+        if (q->k > 0 && seeds) {
+            IMX_HIP(hipMemcpyAsync(seeds, q->seeds, sizeof(int32_t) * q->k, hipMemcpyDeviceToHost, st_));
+            IMX_HIP(hipStreamSynchronize(st_));
+        }
+        if (T)
+            for (int k = 0; k < q->k; ++k) T[k] = q->T[k];
         return IM_OK;
     }
 
@@ -765,7 +803,10 @@ im_status Engine::step()
                 q->fresh = false;
                 q->sweep = 0;
                 q->need_est = true;
-                q->stage = q->park ? Stage::Estimate : Stage::Pick;
+                if (q->park)
+                    q->stage = Stage::Estimate;
+                else
+                    enter_pick(q);
             } else if (q->sweep > q->g->n + 2) {
                 q->stage = Stage::Failed;
                 return set_error(IM_EDEVICE, "propagation did not converge");
@@ -775,9 +816,13 @@ im_status Engine::step()
             break;
         }
         case Stage::Estimate:
-            q->stage = Stage::Built;
             q->need_est = false;
-            q->st.build_ms = now_ms() - q->t_build0;
+            if (q->park) {
+                q->stage = Stage::Built;
+                q->st.build_ms = now_ms() - q->t_build0;
+            } else {
+                q->stage = Stage::Paused;  // estimate terms for a pause after a rebuild
+            }
             break;
         case Stage::Pick:
         case Stage::Levels: {
@@ -798,7 +843,7 @@ im_status Engine::step()
                     q->stage = Stage::Fill;
                     q->sweep = 0;
                 } else {
-                    q->stage = Stage::Pick;
+                    enter_pick(q);
                 }
             } else if (q->level > q->g->n + 8) {
                 q->stage = Stage::Failed;
@@ -891,10 +936,19 @@ im_status im_select_seeds(im_sketch* s, int32_t K, int32_t* seeds_host, double* 
 {
     if (!s) return imx::set_error(IM_EINVAL, "sketch is NULL");
     if (!seeds_host) return imx::set_error(IM_EINVAL, "seeds output is NULL");
-    if (im_status e = s->eng->resume(s->q, K)) return e;
+    if (im_status e = s->eng->resume(s->q, K, -1)) return e;
     if (im_status e = s->eng->run()) return e;
     if (im_status e = finish_prop_counters(s->q)) return e;
     return s->eng->results(s->q, seeds_host, spread_out, est_host, T_host, stats_out);
+}
+
+im_status im_select_seeds_until(im_sketch* s, int32_t K, int32_t k_stop, int32_t* seeds_host, uint64_t* T_host)
+{
+    if (!s) return imx::set_error(IM_EINVAL, "sketch is NULL");
+    if (k_stop < 0) return imx::set_error(IM_EINVAL, "k_stop must be >= 0");
+    if (im_status e = s->eng->resume(s->q, K, k_stop)) return e;
+    if (im_status e = s->eng->run()) return e;
+    return s->eng->partial_results(s->q, seeds_host, T_host);
 }
 
 im_status im_sketch_registers(const im_sketch* s, uint8_t* regs_host)

@@ -40,14 +40,21 @@ def _same(a, b):
     assert a["stats"]["rebuilds"] == b["stats"]["rebuilds"]
 
 
+def _same_as_oracle(r, ref):
+    assert list(r["seeds"]) == list(ref["seeds"])
+    assert list(r["T"]) == list(ref["T"])
+    assert r["est"].tobytes() == ref["est"].tobytes()
+    assert r["spread"] == ref["spread"]
+    assert r["stats"]["rebuilds"] == int(np.count_nonzero(ref["sweeps"][1:]))
+
+
 def test_engine_mix_equals_solo(imx, orc):
     cases = _graphs()
     Gs = [imx.Graph.from_graphgen(g) for g, *_ in cases]
     solo = [_solo(imx, G, J, s, K) for G, (_, J, s, K) in zip(Gs, cases)]
-    # first two against the oracle as well
-    for (g, J, s, K), r in list(zip(cases, solo))[:2]:
-        ref = orc.greedy(g, J, s, K, keep_registers=False)
-        assert list(r["seeds"]) == list(ref["seeds"]) and list(r["T"]) == list(ref["T"])
+    # every query against the oracle as well
+    for (g, J, s, K), r in zip(cases, solo):
+        _same_as_oracle(r, orc.greedy(g, J, s, K, keep_registers=False))
     E = imx.Engine(max_queries=16)
     ids = [E.submit(G, J, s, K) for G, (_, J, s, K) in zip(Gs, cases)]
     _say(f"[engine] {len(ids)} queries")
@@ -130,14 +137,14 @@ def test_engine_many_queries_one_graph(imx):
     E.free()
 
 
-def test_server_results_equal_solo(imx):
+def test_server_results_equal_solo(imx, orc):
     """Continuous batching under a bursty arrival trace: every served result is
-    identical to the query run alone."""
+    identical to the query run alone and to the oracle."""
     from paper_2410_14047_amd import serve
     base = graphgen.rmat(11, 16, seed=3)
-    graphs = {"r11_0.01": imx.Graph.from_graphgen(graphgen.with_p(base, "0.01")),
-              "r11_wc": imx.Graph.from_graphgen(graphgen.with_p(base, "wc")),
-              "er": imx.Graph.from_graphgen(graphgen.with_p(graphgen.erdos_renyi(600, 3000, 2), "0.1"))}
+    host = {"r11_0.01": graphgen.with_p(base, "0.01"), "r11_wc": graphgen.with_p(base, "wc"),
+            "er": graphgen.with_p(graphgen.erdos_renyi(600, 3000, 2), "0.1")}
+    graphs = {k: imx.Graph.from_graphgen(v) for k, v in host.items()}
     rng = np.random.default_rng(5)
     names = sorted(graphs)
     trace, t = [], 0.0
@@ -145,6 +152,8 @@ def test_server_results_equal_solo(imx):
         t += float(rng.exponential(0.002))
         trace.append((t, names[i % 3], int(rng.choice([64, 256])), int(i), int(rng.integers(2, 8))))
     solo = [_solo(imx, graphs[gname], J, seed, K) for (ta, gname, J, seed, K) in trace]
+    for (ta, gname, J, seed, K), r in zip(trace, solo):
+        _same_as_oracle(r, orc.greedy(host[gname], J, seed, K, keep_registers=False))
     for lanes in (None, [256 << 10]):  # one engine; two engines on their own streams
         srv = serve.Server(graphs, max_queries=6, lanes=lanes).start()
         res, makespan = serve.replay(srv, trace)

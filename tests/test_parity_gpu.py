@@ -47,6 +47,9 @@ def assert_parity(orc, gpu, ref, J, seed):
     assert np.array_equal(gpu["Juf"], Ju) and np.array_equal(gpu["Huf"], Hu), "final estimate terms"
     rebuilds = int(np.count_nonzero(ref["sweeps"][1:]))
     assert gpu["stats"]["rebuilds"] == rebuilds
+    # in-place sweeps reach the fixed point no later than synchronous ones
+    assert gpu["stats"]["build_sweeps"] <= int(ref["sweeps"][0]), (gpu["stats"]["build_sweeps"], ref["sweeps"][0])
+    assert gpu["stats"]["total_sweeps"] <= int(ref["sweeps"].sum())
 
 
 def _hub_graph():
@@ -182,98 +185,165 @@ def test_select_twice_is_state_error(imx):
         S2.select(51)
 
 
-# ---------------------------------------------------------------- full-size workload, sampled checks
+# ---------------------------------------------------------------- full-size workloads, pick by pick
 
-_C2 = {}
+def _cover(lg, X, j, seeds):
+    """Covered set of simulation j for a seed prefix (the cascade's result:
+    union of the seeds' live-graph reachability sets), by the oracle."""
+    if len(seeds) == 0:
+        return np.zeros(lg.g.n, np.uint8)
+    return lg.cover_from(int(X[j]), [int(s) for s in seeds])
 
 
-def _c2_graph():
-    if "g" not in _C2:
-        _C2["g"] = graphgen.with_p(graphgen.rmat(20, 16, seed=1), "wc")
-    return _C2["g"]
-
-
-def test_rmat20_wc_full_size_sampled(imx, orc):
-    """RMAT scale 20, weighted cascade, J=512, K=50 -- the benchmark workload --
-    checked on outputs the oracle computes one at a time: sampled registers
-    against closed-form reachability, all estimate terms from the downloaded
-    registers, the first pick, and the final covered sets of sampled
-    simulations against BFS from the seed set."""
-    g = _c2_graph()
-    J, seed, K = 512, 1, 50
-    _say(f"[c2] n={g.n} m={g.m}")
+def stepwise_check(imx, orc, g, J, seed, K, *, reg_samples, reg_sims, full_picks=(), T_sims=None,
+                   extra_reg_picks=(), label=""):
+    """Run the selection of K seeds pick by pick (paused before every pick
+    through the parity hook) and check, at full size, what each pick reads:
+      - every pick equals the oracle's exact argmax over the downloaded
+        (J_u, H_u) with the seeds so far excluded, and its reported estimate
+        equals the oracle's value of those terms;
+      - (J_u, H_u) of sampled rows equal the oracle's terms of those rows;
+      - after the initial build and after every rebuild (and at the picks in
+        `extra_reg_picks`), sampled registers equal the closed form: 0 where
+        the simulation's covered set (cascades of the seeds so far) holds the
+        vertex, else the max rank reachable without entering the covered set of
+        the last rebuild;
+      - at the picks in `full_picks`, every (J_u, H_u) equals the oracle's
+        terms of the downloaded registers (all of them);
+      - T after each pick equals the covered-pair count of the sampled
+        simulations' covered sets, summed over `T_sims` (all J when None) at
+        the picks in `full_picks`.
+    Returns the final results and the number of rebuilds seen."""
+    rng = np.random.default_rng(seed + 7)
     G = imx.Graph.from_graphgen(g)
     S = imx.Sketch(G, J, seed)
     X = S.sim_values()
-    assert np.array_equal(X, orc.sim_values(seed, J))
-    M0 = S.registers()
-    Ju0, Hu0 = S.estimates()
+    assert np.array_equal(X, orc.sim_values(seed, J)), "simulation values"
+    lg = orc.LiveGraph(g)
+    hubs = np.argsort(g.out_degree())[-8:]
+    is_seed = np.zeros(g.n, np.uint8)
+    seeds, expect_est, T_seen = [], [], []
+    last_build, T_old, rebuilds = 0, 0, 0
+    for k in range(K):
+        got_s, got_T = S.select_until(K, k)
+        assert list(got_s) == seeds, f"{label} seeds before pick {k}"
+        T_seen = [int(t) for t in got_T]
+        if k > 0:
+            T = T_seen[-1]
+            if 100 * (T - T_old) > T:  # the rebuild rule after pick k-1 (< K-1)
+                T_old, last_build = T, k
+                rebuilds += 1
+        Ju, Hu = S.estimates()
+        s_k = orc.argmax(Ju, Hu, is_seed)
+        expect_est.append(orc.estimate_value(J, int(Ju[s_k]), int(Hu[s_k])))
+        us = np.unique(np.concatenate([rng.integers(0, g.n, 24), hubs])).astype(np.int32)
+        rows = S.register_rows(us)
+        Jr, Hr = orc.estimates(rows)
+        assert np.array_equal(Ju[us], Jr) and np.array_equal(Hu[us], Hr), f"{label} estimate terms of rows, pick {k}"
+        if k == last_build or k in extra_reg_picks:
+            js = rng.choice(J, reg_sims, replace=False)
+            checked = 0
+            for j in js:
+                cov_now = _cover(lg, X, j, seeds)
+                cov_build = _cover(lg, X, j, seeds[:last_build])
+                for u in rng.choice(us, max(1, reg_samples // reg_sims)):
+                    i = int(np.searchsorted(us, u))
+                    want = 0 if cov_now[u] else lg.reach_max(int(X[j]), seed, int(j), int(u), cov_build)
+                    assert rows[i, j] == want, f"{label} register ({u}, {j}) before pick {k}"
+                    checked += 1
+                # uncovered at the build, covered since: zero; uncovered now: nonzero
+                fresh = np.flatnonzero(cov_now != cov_build)[:200].astype(np.int32)
+                if fresh.size:
+                    assert np.all(S.register_rows(fresh)[:, j] == 0), f"{label} newly covered, sim {j}, pick {k}"
+            assert checked >= min(100, reg_samples)
+        if k in full_picks:
+            M = S.registers()
+            Jf, Hf = orc.estimates(M)
+            assert np.array_equal(Ju, Jf) and np.array_equal(Hu, Hf), f"{label} all estimate terms, pick {k}"
+            if k > 0:
+                sims = range(J) if T_sims is None else T_sims
+                zeros = M == 0
+                assert int(zeros.sum()) == T_seen[-1], f"{label} T equals the covered registers, pick {k}"
+                for j in sims:
+                    assert np.array_equal(zeros[:, j], _cover(lg, X, j, seeds).astype(bool)), f"{label} covered set {j}"
+            del M
+        seeds.append(int(s_k))
+        is_seed[s_k] = 1
     r = S.select(K)
-    Mf = S.registers()
+    assert list(r["seeds"]) == seeds, f"{label} picks"
+    assert [float(e) for e in r["est"]] == expect_est, f"{label} estimates"
+    assert [int(t) for t in r["T"][:K - 1]] == T_seen, f"{label} T"
+    assert r["stats"]["rebuilds"] == rebuilds, f"{label} rebuilds"
+    assert r["spread"] == int(r["T"][-1]) / J
     S.free()
     G.free()
-
-    lg = orc.LiveGraph(g)
-    rng = np.random.default_rng(0)
-    deg = g.out_degree()
-    hubs = np.argsort(deg)[-20:]
-    us = np.concatenate([rng.integers(0, g.n, 150), hubs])
-    js = rng.integers(0, J, us.size)
-    for u, j in zip(us, js):
-        assert M0[u, j] == lg.reach_max(int(X[j]), seed, int(j), int(u)), (u, j)
-
-    Ju, Hu = orc.estimates(M0)
-    assert np.array_equal(Ju0, Ju) and np.array_equal(Hu0, Hu)
-    s0 = orc.argmax(Ju, Hu)
-    assert r["seeds"][0] == s0
-    assert r["est"][0] == orc.estimate_value(J, int(Ju[s0]), int(Hu[s0]))
-    assert len(set(r["seeds"].tolist())) == K
-
-    zeros = Mf == 0
-    assert int(zeros.sum()) == int(r["T"][-1])
-    assert r["spread"] == int(r["T"][-1]) / J
-    for j in rng.integers(0, J, 6):
-        cov = lg.cover_from(int(X[j]), r["seeds"])
-        assert np.array_equal(zeros[:, j], cov.astype(bool)), j
+    return r, rebuilds
 
 
-@pytest.mark.skipif(os.environ.get("IMX_FULL_RMAT24") != "1",
-                    reason="RMAT-24 (16 GiB of registers, minutes of input generation) runs only when "
-                           "IMX_FULL_RMAT24=1")
-@pytest.mark.parametrize("scheme", ["0.01", "trivalency"])
-def test_rmat24_full_size_sampled(imx, orc, scheme):
-    """RMAT scale 24, J=1024: sampled registers against closed-form
-    reachability, every estimate term of sampled rows, first pick, and the
-    covered sets of sampled simulations after K=50 picks."""
-    g = graphgen.with_p(graphgen.rmat(24, 16, seed=1), scheme)
-    J, seed, K = 1024, 1, 50
-    _say(f"[c3 {scheme}] n={g.n} m={g.m}")
+_GRAPHS = {}
+
+
+def _cached_graph(key, make):
+    if key not in _GRAPHS:
+        _GRAPHS[key] = make()
+    return _GRAPHS[key]
+
+
+def test_rmat20_wc_full_size_every_pick(imx, orc):
+    """RMAT scale 20, weighted cascade, J=512, K=50 (the many-rebuild
+    workload): every pick, estimate and rebuild checked against the oracle at
+    full size; all estimate terms and every simulation's covered set at
+    several picks."""
+    g = _cached_graph("rmat20_wc", lambda: graphgen.with_p(graphgen.rmat(20, 16, seed=1), "wc"))
+    _say(f"[c2 every pick] n={g.n} m={g.m}")
+    r, rebuilds = stepwise_check(imx, orc, g, 512, 1, 50, reg_samples=120, reg_sims=8,
+                                 full_picks=(0, 1, 17, 49), extra_reg_picks=(25, 49), label="c2")
+    assert rebuilds >= 10
+    _say(f"[c2 every pick] ok: rebuilds={rebuilds} spread={r['spread']:.1f}")
+
+
+def test_rmat24_p001_full_size_every_pick(imx, orc):
+    """RMAT scale 24, p = 0.01, J=1024, K=50 (16 GiB of registers, offsets
+    above 2^32): every pick and estimate against the oracle's exact argmax of
+    the downloaded terms, sampled registers against the closed form after the
+    initial build and the rebuild, covered sets of sampled vertices."""
+    g = _cached_graph("rmat24_0.01", lambda: graphgen.with_p(graphgen.rmat(24, 16, seed=1), "0.01"))
+    _say(f"[c3 every pick] n={g.n} m={g.m}")
+    r, rebuilds = stepwise_check(imx, orc, g, 1024, 1, 50, reg_samples=120, reg_sims=6,
+                                 extra_reg_picks=(20, 49), label="c3")
+    assert rebuilds >= 1
+    _say(f"[c3 every pick] ok: rebuilds={rebuilds} spread={r['spread']:.1f}")
+
+
+@pytest.mark.skipif(os.environ.get("IMX_FULL_RMAT24_TRI") != "1",
+                    reason="the trivalency variant of RMAT-24 (another 16 GiB build, about two minutes) runs "
+                           "only when IMX_FULL_RMAT24_TRI=1; the p = 0.01 variant always runs")
+def test_rmat24_trivalency_full_size_every_pick(imx, orc):
+    g = _cached_graph("rmat24_tri", lambda: graphgen.with_p(graphgen.rmat(24, 16, seed=1), "trivalency"))
+    _say(f"[c3 tri every pick] n={g.n} m={g.m}")
+    stepwise_check(imx, orc, g, 1024, 1, 50, reg_samples=120, reg_sims=6, label="c3-tri")
+
+
+def test_pause_and_resume_is_invisible(imx, orc):
+    """Pausing before picks (parity hook) changes no output; bad pause points
+    are rejected."""
+    g = graphgen.with_p(graphgen.rmat(12, 16, seed=3), "wc")
+    J, seed, K = 256, 4, 12
+    ref = orc.greedy(g, J, seed, K, keep_registers=False)
     G = imx.Graph.from_graphgen(g)
     S = imx.Sketch(G, J, seed)
-    X = S.sim_values()
-    assert np.array_equal(X, orc.sim_values(seed, J))
-    lg = orc.LiveGraph(g)
-    rng = np.random.default_rng(1)
-    hubs = np.argsort(g.out_degree())[-16:]
-    us = np.concatenate([rng.integers(0, g.n, 120), hubs]).astype(np.int32)
-    rows = S.register_rows(us)
-    Ju0, Hu0 = S.estimates()
-    for i, u in enumerate(us):
-        for j in rng.integers(0, J, 4):
-            assert rows[i, j] == lg.reach_max(int(X[j]), seed, int(j), int(u)), (u, j)
-    Ju_s, Hu_s = orc.estimates(rows)
-    assert np.array_equal(Ju0[us], Ju_s) and np.array_equal(Hu0[us], Hu_s)
-    s0 = orc.argmax(Ju0, Hu0)
+    s3, T3 = S.select_until(K, 3)
+    assert list(s3) == list(ref["seeds"][:3]) and list(T3) == list(ref["T"][:3])
+    with pytest.raises(imx.IMError):
+        S.select_until(K, 2)  # already past pick 2
+    with pytest.raises(imx.IMError):
+        S.select_until(K + 1, 5)  # another K
+    S.select_until(K, 7)
     r = S.select(K)
-    assert r["seeds"][0] == s0
-    assert len(set(r["seeds"].tolist())) == K
-    for j in rng.integers(0, J, 3):
-        cov = lg.cover_from(int(X[j]), r["seeds"]).astype(bool)
-        covered_ids = np.flatnonzero(cov)
-        free_ids = np.flatnonzero(~cov)
-        pick_c = rng.choice(covered_ids, min(2000, covered_ids.size), replace=False).astype(np.int32)
-        pick_f = rng.choice(free_ids, 2000, replace=False).astype(np.int32)
-        assert np.all(S.register_rows(pick_c)[:, j] == 0), j
-        assert np.all(S.register_rows(pick_f)[:, j] != 0), j
+    assert list(r["seeds"]) == list(ref["seeds"]) and list(r["T"]) == list(ref["T"])
+    assert r["est"].tobytes() == ref["est"].tobytes()
+    with pytest.raises(imx.IMError) as ei:
+        S.select_until(K, 1)
+    assert ei.value.status == 4
     S.free()
     G.free()
