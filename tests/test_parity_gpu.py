@@ -225,6 +225,8 @@ def stepwise_check(imx, orc, g, J, seed, K, *, reg_samples, reg_sims, full_picks
     seeds, expect_est, T_seen = [], [], []
     last_build, T_old, rebuilds = 0, 0, 0
     for k in range(K):
+        if k % 10 == 0:
+            _say(f"[{label}] pick {k}/{K}, rebuilds so far {rebuilds}")
         got_s, got_T = S.select_until(K, k)
         assert list(got_s) == seeds, f"{label} seeds before pick {k}"
         T_seen = [int(t) for t in got_T]
