@@ -5,17 +5,14 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "pack_layout.h"
+
 namespace imx {
 
 constexpr int kWaves = 4;             // waves per workgroup in the wave-per-task kernels
 constexpr int kWG = 64 * kWaves;      // workgroup size
 constexpr int kMaxJ = 4096;           // registers per vertex, upper bound
 constexpr int kArgmaxBlocks = 1024;   // partial-argmax workgroups
-constexpr int kBuckets = 1024;        // bucket table over the top bits of the 31-bit X values
-constexpr int kBucketShift = 21;      // X >> 21 selects the bucket
-// LDS words of the X values plus bucket table, padded to 16 bytes so that the
-// per-wave and per-group areas after it keep 8- and 16-byte alignment.
-constexpr int kTableWords = ((kBuckets + 1 + 3) / 4) * 4;
 
 // Pointers in the records below point to device memory.  A record has two
 // views with one layout: the host view (G = false, plain pointers), which host

@@ -990,23 +990,11 @@ __global__ __launch_bounds__(kWG, 6) void k_propagate(const PropArgs* __restrict
 // are identical (the fixed point does not depend on the schedule).
 
 
-constexpr int kPackMax = 16;
-constexpr int kPackWaves = 8;              // waves per workgroup of the packed kernel
-constexpr int kPackWG = 64 * kPackWaves;
-// LDS words per wave of the packed kernel besides the rows: dirty bytes,
-// per-arc arrays (ev, eh, eW, edl, est, ek: 6 x 64), task records (u, e0 lo/hi,
-// prefix, split, touched, active, changed, in_first, in_cnt: 10 x 16 + 1),
-// sector masks (2 x 64, instrumented variant), list buffer.
-constexpr int kPackArcWords = 6 * 64;
-constexpr int kPackTaskWords = 10 * kPackMax + 16;
-__host__ __device__ inline int pack_row_words(int maxJ, int pb) { return (maxJ > pb) ? maxJ / 4 : pb / 4; }
-__host__ __device__ inline int pack_dirty_words(int maxJ, int pb) { return pack_row_words(maxJ, pb) / 4; }  // a byte per row word
-constexpr int kPackBufCap = 128;  // staging entries per wave for the changed in-task list
-__host__ __device__ inline int pack_wave_words(int maxJ, int pb, bool stats)
-{
-    return pack_row_words(maxJ, pb) + pack_dirty_words(maxJ, pb) + kPackArcWords + kPackTaskWords + (stats ? 2 * 64 : 0) +
-           kPackBufCap;
-}
+// The workgroup's LDS layout (X table, then per wave: rows, dirty bytes, arc
+// and task records, sector masks, list buffer) is defined in pack_layout.h;
+// every configuration the launch code can form keeps the alignments the
+// kernel's vector and 64-bit atomic LDS accesses need.
+static_assert(pack_layouts_ok(), "packed-propagation LDS layout misaligned or too large");
 
 int pack_bytes()
 {
@@ -1045,9 +1033,8 @@ __global__ __launch_bounds__(kPackWG, 3) void k_propagate_pack(const PropArgs* _
 
     uint32_t* sX = smem;
     const uint32_t* sT = smem + J;
-    const int XT = ((maxJ + kTableWords) + 3) & ~3;
     const int rw = pack_row_words(maxJ, pb), dw8 = pack_dirty_words(maxJ, pb);
-    uint32_t* wbase = smem + XT + wave * pack_wave_words(maxJ, pb, STATS);
+    uint32_t* wbase = smem + pack_wave_base(maxJ, pb, STATS, wave);
     uint32_t* rows = wbase;                                      // P x Jw words
     uint8_t* dirty8 = reinterpret_cast<uint8_t*>(rows + rw);     // P x Jw bytes
     int* ev = reinterpret_cast<int*>(rows + rw + dw8);
@@ -1066,8 +1053,8 @@ __global__ __launch_bounds__(kPackWG, 3) void k_propagate_pack(const PropArgs* _
     int* T_chg = T_act + kPackMax;
     int* T_in0 = T_chg + kPackMax;
     int* T_inc = T_in0 + kPackMax;
-    unsigned long long* esec = reinterpret_cast<unsigned long long*>(wbase + rw + dw8 + kPackArcWords +
-                                                                     kPackTaskWords);  // STATS only; 8-byte aligned
+    unsigned long long* esec =
+        reinterpret_cast<unsigned long long*>(smem + pack_esec_word(maxJ, pb, STATS, wave));  // STATS only; 8-byte aligned
     int32_t* wbuf = reinterpret_cast<int32_t*>(STATS ? reinterpret_cast<uint32_t*>(esec + 64)
                                                      : reinterpret_cast<uint32_t*>(esec));
     WaveList chl{wbuf, 0, a.chg_list, a.chg_count, kPackBufCap};
@@ -1075,7 +1062,6 @@ __global__ __launch_bounds__(kPackWG, 3) void k_propagate_pack(const PropArgs* _
     unsigned long long c_changed = 0, c_visited = 0;
 
     // next draw of this workgroup's pack sequence: a padding word after the table
-    static_assert(kTableWords > kBuckets + 1, "the bucket table leaves a padding word");
     uint32_t* const s_next = smem + (J + kBuckets + 1);
     if (threadIdx.x == 0) *s_next = 2 * kPackWaves;
     for (int i = threadIdx.x; i < J + kBuckets + 1; i += kPackWG) sX[i] = a.X[i];
@@ -1442,8 +1428,7 @@ int propagate_group_size(int J, int requested)
 
 static size_t pack_lds(int maxJ, bool stats)
 {
-    const int XT = ((maxJ + kTableWords) + 3) & ~3;
-    return sizeof(uint32_t) * ((size_t)XT + (size_t)kPackWaves * (size_t)pack_wave_words(maxJ, pack_bytes(), stats));
+    return sizeof(uint32_t) * (size_t)pack_lds_words(maxJ, pack_bytes(), stats);
 }
 
 template <bool STATS>
