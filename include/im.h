@@ -224,6 +224,36 @@ im_status im_sketch_sim_values(const im_sketch* s, uint32_t* X_host);
 void im_sketch_free(im_sketch* s);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the query of
+ * im_sketch_build(g, J, seed) followed by im_select_seeds(K), with the same
+ * kernels and bit-identical results, but without allocating any device or
+ * pinned host memory.  Its working buffers live in a fixed device array of
+ * 64 MiB that the library holds per device for the life of the process; the
+ * registers live in a buffer the caller passes.
+ *   g             graph on the current device.
+ *   J, seed, K    as for im_sketch_build and im_select_seeds.
+ *   registers_dev device buffer of n*J bytes (uint8, vertex-major), owned by
+ *                 the caller; its contents on entry are ignored, and on return
+ *                 it holds the final registers (covered registers 0), as
+ *                 im_sketch_registers would after im_select_seeds.
+ *   seeds_host    int32[K] output, in pick order.
+ *   spread_out    optional double: T_K / J.
+ *   est_host      optional double[K]: estimate of each pick.
+ *   stream        stream of the call's work (NULL = null stream); the call
+ *                 returns after the work has finished.
+ * Working memory needed: about 24 bytes per vertex, 16 per out-task and 4 per
+ * in-task (a graph of a million vertices fits); a query that needs more than
+ * 64 MiB returns IM_EINVAL and does nothing.  Every call on one device shares
+ * that device's array and overwrites it: calls that overlap on one device
+ * (from several threads, or on several streams) race and must be serialised.
+ * Errors: IM_EINVAL (NULL pointer, bad J or K, working memory above the
+ * maximum), IM_EDEVICE.
+ */
+im_status im_select_seeds_noalloc(const im_graph* g, int32_t J, uint64_t seed, int32_t K, uint8_t* registers_dev,
+                                  int32_t* seeds_host, double* spread_out, double* est_host, void* stream);
+
+/*
  * Engines run many queries (graph, J, seed, K) together: every query follows
  * exactly the steps of im_sketch_build + im_select_seeds, and the engine
  * advances all of them one stage per im_engine_step, sharing kernel launches

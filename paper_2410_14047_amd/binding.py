@@ -61,6 +61,7 @@ EXPORTS = [
     "im_engine_create", "im_engine_submit", "im_engine_step", "im_engine_poll", "im_engine_result",
     "im_engine_info", "im_query_footprint", "im_engine_free", "im_select_seeds_batch",
     "im_engine_set_tuning", "im_engine_get_tuning", "im_set_allocator", "im_engine_counters",
+    "im_select_seeds_noalloc",
 ]
 _VOID = ("im_last_error", "im_graph_free", "im_sketch_free", "im_engine_free", "im_query_footprint")
 
@@ -127,6 +128,7 @@ def lib() -> ctypes.CDLL:
         L.im_select_seeds_batch.argtypes = [i32, P, P, P, P, P, P, P]
         L.im_engine_set_tuning.argtypes = [P, P]
         L.im_engine_get_tuning.argtypes = [P, P]
+        L.im_select_seeds_noalloc.argtypes = [P, i32, u64, i32, P, P, P, P, P]
         for name in EXPORTS:
             if name not in _VOID:
                 getattr(L, name).restype = ctypes.c_int
@@ -240,6 +242,18 @@ def im_select_seeds_until(s, K: int, k_stop: int):
     T = np.zeros(max(k_stop, 1), dtype=np.uint64)
     _check(lib().im_select_seeds_until(s, K, k_stop, _p(seeds), _p(T)))
     return seeds[:k_stop], T[:k_stop]
+
+
+def im_select_seeds_noalloc(g, J: int, seed: int, K: int, registers_dev: int, stream=None):
+    """im_sketch_build + im_select_seeds without device allocation; the
+    registers live in the caller's device buffer at address registers_dev
+    (n*J bytes)."""
+    seeds = np.zeros(K, dtype=np.int32)
+    est = np.zeros(K, dtype=np.float64)
+    spread = ctypes.c_double()
+    _check(lib().im_select_seeds_noalloc(g, J, seed, K, ctypes.c_void_p(registers_dev), _p(seeds),
+                                         ctypes.byref(spread), _p(est), _stream(stream)))
+    return dict(seeds=seeds, spread=spread.value, est=est)
 
 
 def im_sketch_registers(s, n: int, J: int) -> np.ndarray:

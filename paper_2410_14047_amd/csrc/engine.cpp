@@ -43,6 +43,21 @@ static_assert(sizeof(SlotStatus) == 128, "status record size");
 // terms (the parity hook im_select_seeds_until).
 enum class Stage { Fill, Sweeps, Estimate, Pick, Levels, Built, Paused, Done, Failed };
 
+}  // namespace
+
+double estimate_value(int J, uint32_t Ju, unsigned long long Hu)
+{
+    if (Ju == 0) return 0.0;
+    const double alpha = (J == 16) ? 0.673 : (J == 32) ? 0.697 : (J == 64) ? 0.709 : 0.7213 / (1.0 + 1.079 / (double)J);
+    const volatile double scale = alpha * 8589934592.0;
+    const volatile double num = (double)((uint64_t)Ju * Ju);
+    const volatile double den = (double)J * (double)Hu;
+    const volatile double qv = num / den;
+    return scale * qv;
+}
+
+namespace {
+
 double now_ms()
 {
     using namespace std::chrono;
@@ -348,21 +363,8 @@ public:
         for (int k = 0; k < K; ++k)
             if (hs[k] < 0) return set_error(IM_EDEVICE, "argmax found no candidate");
         if (seeds) std::memcpy(seeds, hs.data(), sizeof(int32_t) * K);
-        if (est) {
-            const int J = q->J;
-            const double alpha = (J == 16) ? 0.673 : (J == 32) ? 0.697 : (J == 64) ? 0.709 : 0.7213 / (1.0 + 1.079 / (double)J);
-            const volatile double scale = alpha * 8589934592.0;
-            for (int k = 0; k < K; ++k) {
-                if (hJ[k] == 0) {
-                    est[k] = 0.0;
-                    continue;
-                }
-                const volatile double num = (double)((uint64_t)hJ[k] * hJ[k]);
-                const volatile double den = (double)J * (double)hH[k];
-                const volatile double qv = num / den;
-                est[k] = scale * qv;
-            }
-        }
+        if (est)
+            for (int k = 0; k < K; ++k) est[k] = estimate_value(q->J, hJ[k], hH[k]);
         if (T)
             for (int k = 0; k < K; ++k) T[k] = q->T[k];
         if (spread) *spread = (double)q->T[K - 1] / (double)q->J;

@@ -41,6 +41,11 @@ struct DeviceBlock {
     DeviceAllocator from;
 };
 
+// Reported estimate of a pick (Eq. 7, harmonic form over uncovered
+// registers): alpha_J * 2^33 * Ju^2 / (J * Hu), evaluated in one fixed order
+// without contraction; 0 when Ju = 0.
+double estimate_value(int J, uint32_t Ju, unsigned long long Hu);
+
 hipError_t device_alloc(size_t bytes, DeviceBlock* out);
 void device_free(const DeviceBlock& b);
 
