@@ -39,6 +39,12 @@ WORKLOADS = {
     "rmat24_tri_J1024_K50": dict(kind="rmat", scale=24, ef=16, scheme="trivalency", J=1024, K=50, gseed=1,
                                  sseed=1),
 }
+# Road-network stand-in (the paper's named weak case: high diameter, few arcs
+# per vertex): 1024 x 1024 lattice of two-way links, 10% removed.
+WORKLOADS["road1024_p0.3_J256_K50"] = dict(kind="road", width=1024, drop=0.1, scheme="0.3", J=256, K=50, gseed=1,
+                                           sseed=1)
+WORKLOADS["road1024_p0.6_J256_K50"] = dict(kind="road", width=1024, drop=0.1, scheme="0.6", J=256, K=50, gseed=1,
+                                           sseed=1)
 DEFAULT = "rmat24_p0.01_J1024_K50"
 # Workloads measured beside the default in the same run (same topology, another
 # probability scheme), reported in the line's `variants` field.
@@ -49,6 +55,8 @@ def make_graph(w):
     import graphgen
     if w["kind"] == "rmat":
         g = graphgen.rmat(w["scale"], w["ef"], seed=w["gseed"])
+    elif w["kind"] == "road":
+        g = graphgen.road_grid(w["width"], w["width"], w["drop"], seed=w["gseed"])
     else:
         g = graphgen.erdos_renyi(w["n"], w["m"], w["gseed"])
     return graphgen.with_p(g, w["scheme"])
@@ -398,6 +406,9 @@ def main():
     ap.add_argument("--quality-worlds", type=int, default=200, help="Monte-Carlo worlds per run (quality)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-roofline", action="store_true", help="skip the instrumented byte-count pass")
+    ap.add_argument("--no-tail", action="store_true",
+                    help="run every sweep and cascade level on the full grid (no single-workgroup tail kernels); "
+                         "the profile that the roofline's mean launch time is checked against uses it")
     ap.add_argument("--no-variants", action="store_true",
                     help="measure only the named workload (not the variants reported beside it)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work in cpu_baseline")
@@ -420,6 +431,8 @@ def main():
                          "calibration into profiles/propagate_<workload>_pmc.json and print it")
     ap.add_argument("--pmc-command", default="", help="the command line recorded in the --pmc-summary output")
     args = ap.parse_args()
+    if args.no_tail:
+        os.environ["IMX_TAIL"] = "0"
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the simulation-column "
               f"split across GPUs is not built).", file=sys.stderr)
@@ -547,15 +560,29 @@ def measure(imx, g, w, workload, steps, warmup, roofline, stream):
           file=sys.stderr, flush=True)
 
     if roofline:
+        # The roofline covers the full-grid propagation kernel over every
+        # sweep: one timed step with the tail kernels off (every sweep is then
+        # a k_propagate_pack launch), and the instrumented step (which never
+        # uses them) for the algorithmic bytes of the same launches.
+        prev = os.environ.get("IMX_TAIL")
+        os.environ["IMX_TAIL"] = "0"
+        S = imx.Sketch(G, J, seed, stream=stream)
+        r0 = S.select(K)
+        S.free()
         imx.im_set_profiling(2)
         S = imx.Sketch(G, J, seed, stream=stream)
         rr = S.select(K)
         S.free()
         imx.im_set_profiling(1)
+        if prev is None:
+            del os.environ["IMX_TAIL"]
+        else:
+            os.environ["IMX_TAIL"] = prev
         st = rr["stats"]
         assert list(rr["seeds"]) == list(results[0]["seeds"]), "instrumented run disagrees"
+        assert list(r0["seeds"]) == list(results[0]["seeds"]), "run without tail kernels disagrees"
         bpl = st["prop_alg_bytes"] / st["prop_launches"]
-        tpl = kms / launches * 1e-3
+        tpl = r0["stats"]["prop_kernel_ms"] / r0["stats"]["prop_launches"] * 1e-3
         achieved = bpl / tpl / 1e9
         traffic = pmc_traffic(workload, bpl)
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

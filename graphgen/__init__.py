@@ -20,7 +20,7 @@ from typing import Optional
 import numpy as np
 
 __all__ = [
-    "Graph", "csr_from_edges", "erdos_renyi", "rmat", "barabasi_albert",
+    "Graph", "csr_from_edges", "erdos_renyi", "rmat", "barabasi_albert", "road_grid",
     "uniform_p", "weighted_cascade_p", "trivalency_p", "with_p",
     "save_npz", "load_npz", "cached",
 ]
@@ -164,6 +164,24 @@ def barabasi_albert(n: int, m0: int = 8, seed: int = 0) -> Graph:
 
 
 # ---------------------------------------------------------------- probability schemes
+
+def road_grid(width: int, height: int, drop: float = 0.1, seed: int = 1) -> Graph:
+    """A road-network stand-in with the structure the paper names as its
+    method's weak case (many vertices, few edges, high diameter): a
+    width x height lattice whose horizontal and vertical links are two-way
+    roads (two arcs each), with a seeded fraction `drop` of the links removed.
+    Vertex ids are row-major, so nearby intersections have nearby ids."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = width * height
+    ids = np.arange(n, dtype=np.int64).reshape(height, width)
+    a = np.concatenate([ids[:, :-1].ravel(), ids[:-1, :].ravel()])  # right and down links
+    b = np.concatenate([ids[:, 1:].ravel(), ids[1:, :].ravel()])
+    keep = rng.random(a.size) >= drop
+    a, b = a[keep], b[keep]
+    g = csr_from_edges(n, np.concatenate([a, b]), np.concatenate([b, a]))
+    g.name = f"road{width}x{height}"
+    return g
+
 
 def uniform_p(g: Graph, p: float) -> np.ndarray:
     return np.full(g.m, p, dtype=np.float32)

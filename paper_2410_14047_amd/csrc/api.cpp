@@ -216,6 +216,10 @@ im_status im_graph_load(int64_t n, int64_t m, const int64_t* rowptr_host, const 
     g->ntasks = (int64_t)tu.size();
     g->in_split = in_split;
     g->n_in_tasks = (int64_t)itv.size();
+    for (int64_t v = 0; v < n; ++v) {
+        g->max_out_deg = std::max<int64_t>(g->max_out_deg, rowptr_host[v + 1] - rowptr_host[v]);
+        g->max_in_deg = std::max<int64_t>(g->max_in_deg, irp[v + 1] - irp[v]);
+    }
     float* p_dev = nullptr;
     imx::Arena tmp;  // probabilities, freed after the thresholds are computed
     auto cleanup = [&](im_status st, const std::string& msg) {

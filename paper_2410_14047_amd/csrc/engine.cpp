@@ -23,6 +23,8 @@ namespace {
 // Sweeps / cascade levels per tick at most.  Convergence and the end of a
 // cascade are detected on the device; launches past them return at once.
 constexpr int kMaxRounds = 16;
+// Partial-argmax workgroups per query in graph mode.
+constexpr int kGraphArgmaxBlocks = 32;
 
 // Per-query counters the host reads back every tick (one array per engine).
 struct SlotStatus {
@@ -35,9 +37,14 @@ struct SlotStatus {
     uint32_t ntouched;
     uint32_t conv;       // first sweep of the build that changed nothing (~0u: none yet)
     uint32_t level_end;  // first empty level of the cascade (~0u: running)
-    uint32_t pad[3];
+    uint32_t tail_next;  // after a tail-sweeps launch: the sweep the full-grid path runs next
+    uint32_t lv_next;    // after a tail-levels launch: the level the full-grid path runs next
+    uint32_t cmp_pending;  // after a tail-levels launch: level whose flags await compaction (~0u: none)
+    uint32_t tail_reason;  // why the last tail launch stopped (kTailStop*)
+    uint32_t pad[15];
 };
-static_assert(sizeof(SlotStatus) == 128, "status record size");
+static_assert(sizeof(SlotStatus) == 192, "status record size");
+
 
 // Paused: stopped before pick `pause_k` with current registers and estimate
 // terms (the parity hook im_select_seeds_until).
@@ -97,6 +104,11 @@ struct Query {
     bool need_est = false;  // the next pick must recompute the estimate terms (after a build)
     int sweep = 0;
     int level = 1;
+    uint32_t lv_pending = ~0u;    // level whose flags the next step must compact first (~0u: none)
+    bool small_front = false;     // the last sweep (level) seen left a frontier small enough for a tail kernel
+    int tail_kind = 0;            // this step: 1 tail sweeps, 2 tail levels, 0 none
+    bool tails_ok = false;        // tail kernels may serve this query (engine tail mode and graph degrees)
+    int32_t* chg_list2 = nullptr; // second in-task list of the tail sweeps
     int k = 0;
     uint32_t cascade_id = 0;
     uint64_t T_old = 0;
@@ -138,10 +150,20 @@ public:
         // argument records of one tick: at most kMaxRounds x (prep, propagate,
         // mark) or kMaxRounds x (level, compaction) plus a few per query, and
         // one 256-byte alignment per launch
-        static_assert(sizeof(PrepArgs) + sizeof(PropArgs) + sizeof(MarkArgs) <= 3 * 256, "sweep records");
-        static_assert(sizeof(LevelArgs) + sizeof(LevelCompactArgs) <= 3 * 256, "level records");
+        // Per query and step at most: per round prep, two propagation
+        // records (graph mode with different kernels for the first and later
+        // sweeps), mark, level and compaction; plus fill, estimate, argmax,
+        // seed, tail prep, tail sweeps, pending compaction, tail levels and
+        // finalize.  Every launch's array starts on 256 bytes.
+        static_assert(sizeof(PrepArgs) + 2 * sizeof(PropArgs) + sizeof(MarkArgs) + sizeof(LevelArgs) +
+                              sizeof(LevelCompactArgs) <= 6 * 384,
+                      "round records");
+        static_assert(sizeof(FillArgs) + sizeof(EstArgs) + sizeof(ArgmaxArgs) + sizeof(SeedArgs) + sizeof(PrepArgs) +
+                              sizeof(TailSweepArgs) + sizeof(LevelCompactArgs) + sizeof(TailLevelArgs) +
+                              sizeof(FinArgs) <= 9 * 384,
+                      "step records");
         const size_t chunks = ((size_t)cap_ + kMaxBatch - 1) / kMaxBatch;
-        args_cap_ = (size_t)cap_ * (kMaxRounds * 3 * 256 + 2048) + chunks * (kMaxRounds * 5 + 16) * 256;
+        args_cap_ = (size_t)cap_ * (kMaxRounds * 6 + 9) * 384 + chunks * (kMaxRounds * 6 + 9) * 256;
         IMX_HIP(bufs_.alloc(&args_dev_, args_cap_));
         IMX_HIP(hipHostMalloc(reinterpret_cast<void**>(&args_host_), args_cap_, 0));
         // timing-only events: no system-scope fence at record (a fenced record
@@ -158,6 +180,12 @@ public:
         if (set_tuning(t) != IM_OK) return IM_EINVAL;
         // Cap on the workgroups of a propagation launch (schedule tests: few
         // workgroups make every one of them take many packs).
+        // Tail kernels for small frontiers (on unless IMX_TAIL=0; limits by
+        // environment for experiments).
+        if (const char* v = std::getenv("IMX_TAIL")) tail_mode_ = std::atoi(v);
+        if (const char* v = std::getenv("IMX_TAIL_ROWS")) tail_rows_ = std::max(0, std::atoi(v));
+        if (const char* v = std::getenv("IMX_TAIL_TASKS")) tail_tasks_ = std::max(1, std::atoi(v));
+        if (const char* v = std::getenv("IMX_TAIL_ROUNDS")) tail_rounds_ = std::max(1, std::atoi(v));
         if (const char* v = std::getenv("IMX_PROP_GRID")) {
             prop_grid_cap_ = std::atoi(v);
             if (prop_grid_cap_ < 1) return set_error(IM_EINVAL, "IMX_PROP_GRID must be >= 1");
@@ -183,8 +211,9 @@ public:
     {
         const size_t n = (size_t)g->n, nt = (size_t)std::max<int64_t>(g->ntasks, 1);
         const size_t nit = (size_t)std::max<int64_t>(g->n_in_tasks, 1), bmw = (n + 31) / 32;
-        return n * (size_t)J + n * (4 + 8 + 1 + 4 * 2) + (size_t)flag_bytes((int64_t)n) * 2 + bmw * 8 + nt * 16 +
-               nit * 4 + ((size_t)J + kTableWords) * 4 +
+        return n * (size_t)J + n * (4 + 8 + 1 + 4 * 2) + (size_t)flag_bytes((int64_t)n) * 2 +
+               (size_t)blk_bytes((int64_t)n) * 2 + bmw * 8 + nt * 16 +
+               nit * 8 + ((size_t)J + kTableWords) * 4 +
                (size_t)kArgmaxBlocks * 16 + (size_t)std::max(K, 1) * 16 + 4096;
     }
 
@@ -224,7 +253,8 @@ public:
             A.alloc(&q->sw.act_tasks[0], nt) || A.alloc(&q->sw.act_tasks[1], nt) || A.alloc(&q->sw.chg_list, nit) ||
             A.alloc(&q->is_seed, n) || A.alloc(&q->best, 1) || A.alloc(&q->c.q[0], nt) || A.alloc(&q->c.q[1], nt) ||
             A.alloc(&q->c.lv8, flag_bytes(n)) || A.alloc(&q->c.touched, n) || A.alloc(&q->c.touch_stamp, n) ||
-            A.alloc(&q->am.pJ, kArgmaxBlocks) || A.alloc(&q->am.pH, kArgmaxBlocks) || A.alloc(&q->am.pid, kArgmaxBlocks)) {
+            A.alloc(&q->am.pJ, kArgmaxBlocks) || A.alloc(&q->am.pH, kArgmaxBlocks) || A.alloc(&q->am.pid, kArgmaxBlocks) ||
+            A.alloc(&q->chg_list2, nit) || A.alloc(&q->sw.act_blk, blk_bytes(n)) || A.alloc(&q->c.lv_blk, blk_bytes(n))) {
             A.release();
             return set_error(IM_ENOMEM, "device allocation failed");
         }
@@ -251,6 +281,8 @@ public:
         if (e == hipSuccess) e = hipMemsetAsync(q->is_seed, 0, n, st_);
         if (e == hipSuccess) e = hipMemsetAsync(q->sw.act8, 0, flag_bytes(n), st_);
         if (e == hipSuccess) e = hipMemsetAsync(q->c.lv8, 0, flag_bytes(n), st_);
+        if (e == hipSuccess) e = hipMemsetAsync(q->sw.act_blk, 0, blk_bytes(n), st_);
+        if (e == hipSuccess) e = hipMemsetAsync(q->c.lv_blk, 0, blk_bytes(n), st_);
         if (e == hipSuccess) e = hipMemsetAsync(q->c.touch_stamp, 0, sizeof(uint32_t) * n, st_);
         if (e == hipSuccess && q->pc) e = hipMemsetAsync(q->pc, 0, sizeof(PropCounters), st_);
         if (e == hipSuccess && q->vstamp) e = hipMemsetAsync(q->vstamp, 0, sizeof(uint32_t) * n, st_);
@@ -261,6 +293,7 @@ public:
         }
         q->stage = Stage::Fill;
         q->fresh = true;
+        q->tails_ok = tail_mode_ == 1 || (tail_mode_ == 2 && std::max(g->max_out_deg, g->max_in_deg) <= kTailAutoDegree);
         q->t_build0 = now_ms();
         used_ += A.bytes;
         slots_[slot] = q.get();
@@ -437,6 +470,16 @@ private:
     int cap_;
     size_t budget_;
     int64_t prop_grid_cap_ = 0;  // IMX_PROP_GRID (0: none)
+    // Tail kernels: a query whose last sweep changed at most tail_rows_ rows
+    // (or whose next level has at most tail_tasks_ tasks, or a new cascade)
+    // runs up to tail_rounds_ sweeps (levels) in one single-workgroup launch;
+    // the kernels hand back frontiers beyond tail_tasks_ tasks.
+    // 0 off, 1 on, 2 (default) for graphs of bounded degree only: with hubs
+    // (power-law graphs) a few changed rows have thousands of in-arcs, so
+    // small frontiers rarely stay small for a single workgroup.
+    int tail_mode_ = 2;
+    static constexpr int64_t kTailAutoDegree = 64;
+    int tail_rows_ = 64, tail_tasks_ = 64, tail_rounds_ = 256;
     size_t used_ = 0;
     int64_t next_id_ = 1;
     std::vector<Query*> slots_;
@@ -493,17 +536,29 @@ im_status Engine::step()
             out.emplace_back(v.begin() + i, v.begin() + std::min(v.size(), i + kMaxBatch));
         return out;
     };
-    std::vector<Query*> fill_q, sweep_q, est_q, pick_q, level_q;
+    const bool stats = profiling_level() >= 2;
+    // Small frontiers go to the tail kernels (not in instrumented runs, whose
+    // counters cover the full-grid propagation kernel only).
+    const bool tails = tail_mode_ != 0 && !stats;
+    std::vector<Query*> fill_q, sweep_q, est_q, pick_q, level_q, tailsw_q, taillv_q, cmp_q;
+    for (Query* q : act) q->tail_kind = 0;
     for (Query* q : act) {
         switch (q->stage) {
         case Stage::Fill: fill_q.push_back(q); sweep_q.push_back(q); break;
-        case Stage::Sweeps: sweep_q.push_back(q); break;
+        case Stage::Sweeps: (tails && q->tails_ok && q->small_front ? tailsw_q : sweep_q).push_back(q); break;
         case Stage::Estimate: est_q.push_back(q); break;
         case Stage::Pick:
             pick_q.push_back(q);
-            level_q.push_back(q);
+            (tails && q->tails_ok ? taillv_q : level_q).push_back(q);
             break;
-        case Stage::Levels: level_q.push_back(q); break;
+        case Stage::Levels:
+            if (q->lv_pending != ~0u) {
+                cmp_q.push_back(q);
+                level_q.push_back(q);
+            } else {
+                (tails && q->tails_ok && q->small_front ? taillv_q : level_q).push_back(q);
+            }
+            break;
         default: break;
         }
     }
@@ -512,12 +567,40 @@ im_status Engine::step()
         q->level = 1;
     }
 
-    // ---- build all launches (argument records) of this tick
+    // ---- build all launches (argument records) of this tick.  In graph mode
+    // every launch list holds every running query, with the records of the
+    // queries outside that launch's stage inactive: the launch sequence of a
+    // step then depends only on the admitted queries, and its captured graph
+    // replays until one finishes or another is admitted.
+    const bool graph_mode = tune_.use_graphs != 0 && !stats;
+    using Member = std::pair<Query*, bool>;
+    auto members = [&](const std::vector<Query*>& v) {
+        std::vector<Member> out;
+        if (!graph_mode) {
+            for (Query* q : v) out.push_back({q, true});
+        } else {
+            for (Query* q : act) out.push_back({q, std::find(v.begin(), v.end(), q) != v.end()});
+        }
+        return out;
+    };
+    auto mchunks = [](const std::vector<Member>& v) {
+        std::vector<std::vector<Member>> out;
+        for (size_t i = 0; i < v.size(); i += kMaxBatch)
+            out.emplace_back(v.begin() + i, v.begin() + std::min(v.size(), i + kMaxBatch));
+        return out;
+    };
+    auto with = [](auto rec, bool active) {
+        rec.active = active ? 1 : 0;
+        return rec;
+    };
+    for (Query* q : tailsw_q) q->tail_kind = 1;
+    for (Query* q : taillv_q) q->tail_kind = 2;
+
     std::vector<Launch<FillArgs>> L_fill;
-    for (auto& ch : chunks(fill_q)) {
+    for (auto& ch : mchunks(members(fill_q))) {
         Launch<FillArgs> L;
-        for (Query* q : ch) {
-            L.args.push_back(FillArgs{q->M, q->g->n, q->J, q->fresh ? 1 : 0, q->seed});
+        for (auto [q, on] : ch) {
+            L.args.push_back(with(FillArgs{q->M, q->g->n, q->J, q->fresh ? 1 : 0, q->seed}, on));
             const int64_t rows_per_wg = 256 / row_lanes(q->J);
             L.want.push_back(std::min<int64_t>(cus * 16, (q->g->n + rows_per_wg - 1) / rows_per_wg));
         }
@@ -528,24 +611,27 @@ im_status Engine::step()
         std::vector<Launch<PropArgs>> prop_first, prop_rest;
         std::vector<Launch<MarkArgs>> mark;
     };
-    std::vector<SweepRound> rounds(sweep_q.empty() ? 0 : nr);
+    const std::vector<Member> sweep_m = members(sweep_q);
+    std::vector<SweepRound> rounds(sweep_m.empty() ? 0 : nr);
     int full_first = 0, full_rest = 0;
-    if (!sweep_q.empty()) {
+    if (!sweep_m.empty()) {
         int maxJ = 0;
-        for (Query* q : sweep_q) maxJ = std::max(maxJ, q->J);
-        IMX_HIP(propagate_full_grid(maxJ, gs_first_, profiling_level() >= 2, &full_first));
-        IMX_HIP(propagate_full_grid(maxJ, gs_rest_, profiling_level() >= 2, &full_rest));
+        for (auto [q, on] : sweep_m) maxJ = std::max(maxJ, q->J);
+        IMX_HIP(propagate_full_grid(maxJ, gs_first_, stats, &full_first));
+        IMX_HIP(propagate_full_grid(maxJ, gs_rest_, stats, &full_rest));
     }
+    // graph mode with one kernel choice for all sweeps: a single propagation list
+    const bool one_prop_list = graph_mode && gs_first_ == gs_rest_;
     for (int b = 0; b < (int)rounds.size(); ++b) {
-        for (auto& ch : chunks(sweep_q)) {
+        for (auto& ch : mchunks(sweep_m)) {
             Launch<PrepArgs> P;
             Launch<PropArgs> F, R;
             Launch<MarkArgs> K;
-            for (Query* q : ch) {
+            for (auto [q, on] : ch) {
                 const int s = q->sweep + b;
                 const GraphDev gd = q->g->dev();
                 const int64_t nwords = (q->g->n + 31) / 32;
-                P.args.push_back(PrepArgs{q->sw, q->g->task_start, q->g->n, nwords, s});
+                P.args.push_back(with(PrepArgs{q->sw, q->g->task_start, q->g->n, nwords, s}, on));
                 P.want.push_back(std::min<int64_t>(cus * 4, (q->g->n + 16 * kWG - 1) / (16 * kWG)));
                 PropArgs pa{gd,
                             q->X,
@@ -562,14 +648,22 @@ im_status Engine::step()
                             &q->sw.rows_changed[s & 3],
                             q->pc,
                             q->vstamp,
-                            ++q->prop_launch_id};
-                Launch<PropArgs>& T = (s == 0) ? F : R;
-                const int gsel = s == 0 ? gs_first_ : gs_rest_;
-                const int lanes = propagate_group_size(q->J, gsel), thr = propagate_wg_threads(gsel);
-                T.args.push_back(pa);
-                T.want.push_back((q->g->ntasks * lanes + thr - 1) / thr);
-                T.maxJ = std::max(T.maxJ, q->J);
-                K.args.push_back(MarkArgs{gd, q->sw, s, tune_.dense_div});
+                            on ? ++q->prop_launch_id : q->prop_launch_id};
+                auto add_prop = [&](Launch<PropArgs>& T, int gsel, bool act_here) {
+                    const int lanes = propagate_group_size(q->J, gsel), thr = propagate_wg_threads(gsel);
+                    T.args.push_back(with(pa, act_here));
+                    T.want.push_back((q->g->ntasks * lanes + thr - 1) / thr);
+                    T.maxJ = std::max(T.maxJ, q->J);
+                };
+                if (one_prop_list) {
+                    add_prop(R, gs_rest_, on);
+                } else if (graph_mode) {
+                    add_prop(F, gs_first_, on && s == 0);
+                    add_prop(R, gs_rest_, on && s != 0);
+                } else {
+                    add_prop(s == 0 ? F : R, s == 0 ? gs_first_ : gs_rest_, on);
+                }
+                K.args.push_back(with(MarkArgs{gd, q->sw, s, tune_.dense_div}, on));
                 K.want.push_back(std::min<int64_t>(cus * 4, (q->g->n_in_tasks + kWaves - 1) / kWaves));
             }
             rounds[b].prep.push_back(std::move(P));
@@ -582,10 +676,10 @@ im_status Engine::step()
     std::vector<Query*> est_all = est_q;
     for (Query* q : pick_q)
         if (q->need_est) est_all.push_back(q);  // estimate terms after every build
-    for (auto& ch : chunks(est_all)) {
+    for (auto& ch : mchunks(members(est_all))) {
         Launch<EstArgs> L;
-        for (Query* q : ch) {
-            L.args.push_back(EstArgs{q->M, q->g->n, q->J, q->Ju, q->Hu});
+        for (auto [q, on] : ch) {
+            L.args.push_back(with(EstArgs{q->M, q->g->n, q->J, q->Ju, q->Hu}, on));
             const int64_t rows_per_wg = kWG / row_lanes(q->J) * kRowBatch;
             L.want.push_back(std::min<int64_t>(cus * 16, (q->g->n + rows_per_wg - 1) / rows_per_wg));
         }
@@ -593,51 +687,110 @@ im_status Engine::step()
     }
     std::vector<Launch<ArgmaxArgs>> L_am;
     std::vector<Launch<SeedArgs>> L_seed;
-    for (auto& ch : chunks(pick_q)) {
+    for (auto& ch : mchunks(members(pick_q))) {
         Launch<ArgmaxArgs> L;
         Launch<SeedArgs> S;
-        for (Query* q : ch) {
-            const int nparts = (int)std::min<int64_t>(kArgmaxBlocks, (q->g->n + 255) / 256);
-            L.args.push_back(ArgmaxArgs{q->Ju, q->Hu, q->is_seed, q->g->n, q->am, q->best, std::max(nparts, 1)});
+        for (auto [q, on] : ch) {
+            // graph mode: few partial workgroups per query (every query's are launched every step)
+            const int nparts =
+                (int)std::min<int64_t>(graph_mode ? kGraphArgmaxBlocks : kArgmaxBlocks, (q->g->n + 255) / 256);
+            L.args.push_back(
+                with(ArgmaxArgs{q->Ju, q->Hu, q->is_seed, q->g->n, q->am, q->best, std::max(nparts, 1)}, on));
             L.want.push_back(std::max(nparts, 1));
-            S.args.push_back(SeedArgs{q->g->dev(), q->best, q->k, q->M, q->J, q->is_seed, q->seeds, q->pickJ, q->pickH,
-                                      q->Ju, q->Hu, q->c, q->cascade_id});
+            S.args.push_back(with(SeedArgs{q->g->dev(), q->best, q->k, q->M, q->J, q->is_seed, q->seeds, q->pickJ,
+                                           q->pickH, q->Ju, q->Hu, q->c, q->cascade_id},
+                                  on));
             S.want.push_back(1);
         }
         L_am.push_back(std::move(L));
         L_seed.push_back(std::move(S));
     }
-    std::vector<std::vector<Launch<LevelArgs>>> L_lvl(level_q.empty() ? 0 : nr);
-    std::vector<std::vector<Launch<LevelCompactArgs>>> L_cmp(level_q.empty() ? 0 : nr);
+    const std::vector<Member> level_m = members(level_q);
+    std::vector<std::vector<Launch<LevelArgs>>> L_lvl(level_m.empty() ? 0 : nr);
+    std::vector<std::vector<Launch<LevelCompactArgs>>> L_cmp(level_m.empty() ? 0 : nr);
     int full_level = 0;
-    if (!level_q.empty()) {
+    if (!level_m.empty()) {
         int maxJ = 0;
-        for (Query* q : level_q) maxJ = std::max(maxJ, q->J);
+        for (auto [q, on] : level_m) maxJ = std::max(maxJ, q->J);
         IMX_HIP(cascade_level_full_grid(maxJ, &full_level));
     }
     for (int b = 0; b < (int)L_lvl.size(); ++b)
-        for (auto& ch : chunks(level_q)) {
+        for (auto& ch : mchunks(level_m)) {
             Launch<LevelArgs> L;
             Launch<LevelCompactArgs> C;
-            for (Query* q : ch) {
+            for (auto [q, on] : ch) {
                 const int t = q->level + b;
-                L.args.push_back(LevelArgs{q->g->dev(), q->X, q->J, q->M, q->c, t});
+                L.args.push_back(with(LevelArgs{q->g->dev(), q->X, q->J, q->M, q->c, t}, on));
                 L.want.push_back((q->g->ntasks + kWaves - 1) / kWaves);
                 L.maxJ = std::max(L.maxJ, q->J);
-                C.args.push_back(LevelCompactArgs{q->g->task_start, q->g->n, q->c, t, q->cascade_id});
+                C.args.push_back(with(LevelCompactArgs{q->g->task_start, q->g->n, q->c, t, q->cascade_id}, on));
                 C.want.push_back(std::min<int64_t>(cus * 4, (q->g->n + 16 * kWG - 1) / (16 * kWG)));
             }
             L_lvl[b].push_back(std::move(L));
             L_cmp[b].push_back(std::move(C));
         }
+    // finalize (it runs only once a cascade has ended), for the queries in
+    // full-grid levels and in tail levels
+    std::vector<Query*> fin_q = level_q;
+    fin_q.insert(fin_q.end(), taillv_q.begin(), taillv_q.end());
     std::vector<Launch<FinArgs>> L_fin;
-    for (auto& ch : chunks(level_q)) {  // each runs only once its cascade has ended
+    for (auto& ch : mchunks(members(fin_q))) {
         Launch<FinArgs> L;
-        for (Query* q : ch) {
-            L.args.push_back(FinArgs{q->M, q->J, q->Ju, q->Hu, q->c});
+        for (auto [q, on] : ch) {
+            L.args.push_back(with(FinArgs{q->M, q->J, q->Ju, q->Hu, q->c}, on));
             L.want.push_back(std::min<int64_t>(cus * 8, (q->g->n + 4 * kWaves - 1) / (4 * kWaves)));
         }
         L_fin.push_back(std::move(L));
+    }
+
+    // tail sweeps: the prep step of the first sweep, then the tail kernel
+    std::vector<Launch<PrepArgs>> L_tprep;
+    std::vector<Launch<TailSweepArgs>> L_tsw;
+    for (auto& ch : mchunks(members(tailsw_q))) {
+        Launch<PrepArgs> P;
+        Launch<TailSweepArgs> T;
+        for (auto [q, on] : ch) {
+            const int s0 = q->sweep;
+            const int64_t nwords = (q->g->n + 31) / 32;
+            P.args.push_back(with(PrepArgs{q->sw, q->g->task_start, q->g->n, nwords, s0}, on));
+            P.want.push_back(std::min<int64_t>(cus * 4, (q->g->n + 16 * kWG - 1) / (16 * kWG)));
+            SlotStatus* S = status_dev_ + q->slot;
+            T.args.push_back(with(TailSweepArgs{q->g->dev(), q->X, q->J, q->M, q->sw, q->chg_list2, &S->tail_next, s0,
+                                                tail_rounds_, tune_.dense_div, (int64_t)kTailCap,
+                                                (int64_t)tail_tasks_, &S->tail_reason},
+                                  on));
+            T.want.push_back(1);
+            T.maxJ = std::max(T.maxJ, q->J);
+        }
+        L_tprep.push_back(std::move(P));
+        L_tsw.push_back(std::move(T));
+    }
+    // pending compactions (a tail-levels launch flagged a level's heads)
+    std::vector<Launch<LevelCompactArgs>> L_pcmp;
+    for (auto& ch : mchunks(members(cmp_q))) {
+        Launch<LevelCompactArgs> C;
+        for (auto [q, on] : ch) {
+            C.args.push_back(
+                with(LevelCompactArgs{q->g->task_start, q->g->n, q->c, on ? (int)q->lv_pending : 0, q->cascade_id}, on));
+            C.want.push_back(std::min<int64_t>(cus * 4, (q->g->n + 16 * kWG - 1) / (16 * kWG)));
+            if (on) q->lv_pending = ~0u;
+        }
+        L_pcmp.push_back(std::move(C));
+    }
+    // tail levels: a new cascade (after its seed step) or a small frontier
+    std::vector<Launch<TailLevelArgs>> L_tlv;
+    for (auto& ch : mchunks(members(taillv_q))) {
+        Launch<TailLevelArgs> T;
+        for (auto [q, on] : ch) {
+            SlotStatus* S = status_dev_ + q->slot;
+            T.args.push_back(with(TailLevelArgs{q->g->dev(), q->X, q->J, q->M, q->c, &S->lv_next, &S->cmp_pending,
+                                                q->level, tail_rounds_, (uint32_t)tail_tasks_, q->cascade_id,
+                                                &S->tail_reason},
+                                  on));
+            T.want.push_back(1);
+            T.maxJ = std::max(T.maxJ, q->J);
+        }
+        L_tlv.push_back(std::move(T));
     }
 
     // ---- stage argument records, one copy; the tick's launch structure
@@ -653,29 +806,44 @@ im_status Engine::step()
         for (int i = 0; i <= L.B.nq; ++i) key.push_back(L.B.wg0[i]);
         return L.dev != nullptr;
     };
+    // graph mode launches every query's workgroups for every kind: the grids of
+    // the grid-stride kernels are capped in total (split by query size)
+    const int64_t gcap = graph_mode ? (int64_t)cus * 8 : 0;
     bool ok = true;
-    for (auto& L : L_fill) ok &= finish(0, L, 0);
+    for (auto& L : L_fill) ok &= finish(0, L, gcap);
     for (auto& R : rounds) {
-        for (auto& L : R.prep) ok &= finish(1, L, 0);
+        for (auto& L : R.prep) ok &= finish(1, L, gcap);
         for (auto& L : R.prop_first) ok &= finish(2, L, prop_cap(full_first));
         for (auto& L : R.prop_rest) ok &= finish(3, L, prop_cap(full_rest));
         for (auto& L : R.mark) ok &= finish(4, L, (int64_t)cus * 4);
     }
-    for (auto& L : L_est) ok &= finish(5, L, 0);
+    for (auto& L : L_est) ok &= finish(5, L, gcap);
     for (auto& L : L_am) ok &= finish(6, L, 0);
     for (auto& L : L_seed) ok &= finish(7, L, 0);
     for (auto& R : L_lvl)
         for (auto& L : R) ok &= finish(8, L, full_level);
     for (auto& R : L_cmp)
-        for (auto& L : R) ok &= finish(9, L, 0);
-    for (auto& L : L_fin) ok &= finish(10, L, 0);
+        for (auto& L : R) ok &= finish(9, L, gcap);
+    for (auto& L : L_fin) ok &= finish(10, L, gcap);
+    auto one_each = [](auto& L) {  // tail kernels: one workgroup per query
+        for (int i = 0; i <= L.B.nq; ++i) L.B.wg0[i] = i;
+    };
+    for (auto& L : L_tprep) ok &= finish(11, L, gcap);
+    for (auto& L : L_tsw) {
+        ok &= finish(12, L, 0);
+        one_each(L);
+    }
+    for (auto& L : L_pcmp) ok &= finish(13, L, gcap);
+    for (auto& L : L_tlv) {
+        ok &= finish(14, L, 0);
+        one_each(L);
+    }
     if (!ok) return set_error(IM_EINVAL, "too many queries for one tick's argument buffer");
 
     // ---- the tick's work, in dependency order: argument records in, kernels,
     // status records out.  `timed` adds the HIP events of the per-phase and
     // per-launch times (not recorded in graph mode).
-    const bool stats = profiling_level() >= 2;
-    const bool sweeping = !rounds.empty(), cascading = !L_lvl.empty();
+    const bool sweeping = !rounds.empty() || !L_tsw.empty(), cascading = !L_lvl.empty() || !L_tlv.empty();
     int ne = 0;
     auto issue = [&](bool timed, hipStream_t sx) -> hipError_t {
         hipError_t e = hipMemcpyAsync(args_dev_, args_host_, args_off_, hipMemcpyHostToDevice, sx);
@@ -685,6 +853,10 @@ im_status Engine::step()
         if (sweeping) ev(ph_[0]);
         for (auto& L : L_fill)
             if (e == hipSuccess) e = launch_fill(L.dev, L.B, sx);
+        for (auto& L : L_tprep)
+            if (e == hipSuccess) e = launch_sweep_prep(L.dev, L.B, sx);
+        for (auto& L : L_tsw)
+            if (e == hipSuccess) e = launch_tail_sweeps(L.dev, L.B, L.maxJ, sx);
         for (auto& R : rounds) {
             for (auto& L : R.prep)
                 if (e == hipSuccess) e = launch_sweep_prep(L.dev, L.B, sx);
@@ -709,6 +881,10 @@ im_status Engine::step()
             if (e == hipSuccess) e = launch_argmax(L_am[i].dev, L_am[i].B, fin, sx);
             if (e == hipSuccess) e = launch_cascade_seed(L_seed[i].dev, L_seed[i].B, sx);
         }
+        for (auto& L : L_tlv)
+            if (e == hipSuccess) e = launch_tail_levels(L.dev, L.B, L.maxJ, sx);
+        for (auto& L : L_pcmp)
+            if (e == hipSuccess) e = launch_cascade_compact(L.dev, L.B, sx);
         for (size_t b = 0; b < L_lvl.size(); ++b) {
             for (auto& L : L_lvl[b])
                 if (e == hipSuccess) e = launch_cascade_level(L.dev, L.B, L.maxJ, sx);
@@ -723,7 +899,6 @@ im_status Engine::step()
         return e;
     };
 
-    const bool graph_mode = tune_.use_graphs != 0 && !stats;
     const bool timed = !graph_mode && profiling_level() >= 1;  // per-launch and per-phase events
     hipStream_t cs = st_;  // stream of this tick's work
     if (graph_mode) {
@@ -790,10 +965,14 @@ im_status Engine::step()
         switch (q->stage) {
         case Stage::Fill:
         case Stage::Sweeps: {
-            q->st.prop_kernel_ms += prop_ms / (double)sweep_q.size();
             q->st.propagate_ms += sweep_phase_ms;
-            q->st.prop_launches += nr;
-            q->sweep += nr;
+            if (q->tail_kind == 1) {
+                q->sweep = (int)S.tail_next;
+            } else {
+                q->st.prop_kernel_ms += prop_ms / (double)sweep_q.size();
+                q->st.prop_launches += nr;
+                q->sweep += nr;
+            }
             if (S.conv != ~0u) {  // sweep S.conv (0-based) changed nothing: the build is complete
                 const int sweeps = (int)S.conv + 1;
                 q->st.total_sweeps += sweeps;
@@ -814,6 +993,10 @@ im_status Engine::step()
                 return set_error(IM_EDEVICE, "propagation did not converge");
             } else {
                 q->stage = Stage::Sweeps;
+                q->small_front = (q->tail_kind == 1)
+                                     ? S.tail_reason == kTailStopRounds
+                                     : (S.dense[q->sweep & 3] == 0u &&
+                                        S.rows_changed[(q->sweep - 1) & 3] <= (unsigned long long)tail_rows_);
             }
             break;
         }
@@ -830,7 +1013,12 @@ im_status Engine::step()
         case Stage::Levels: {
             q->need_est = false;
             q->st.cascade_ms += cascade_phase_ms;
-            q->level += nr;
+            if (q->tail_kind == 2) {
+                q->level = (int)S.lv_next;
+                q->lv_pending = S.cmp_pending;
+            } else {
+                q->level += nr;
+            }
             if (S.level_end != ~0u) {  // the cascade ended and was finalized in this tick
                 q->st.cascade_levels += S.level_end - 1u;
                 const uint64_t T = S.T;
@@ -844,6 +1032,7 @@ im_status Engine::step()
                     ++q->st.rebuilds;
                     q->stage = Stage::Fill;
                     q->sweep = 0;
+                    q->small_front = false;
                 } else {
                     enter_pick(q);
                 }
@@ -852,6 +1041,8 @@ im_status Engine::step()
                 return set_error(IM_EDEVICE, "cascade did not terminate");
             } else {
                 q->stage = Stage::Levels;
+                q->small_front = (q->tail_kind == 2) ? S.tail_reason == kTailStopRounds
+                                                     : S.qsize[q->level & 3] <= (uint32_t)tail_tasks_;
             }
             break;
         }

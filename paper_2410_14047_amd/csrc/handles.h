@@ -95,6 +95,7 @@ struct im_graph {
     int32_t* in_task_start = nullptr;
     int64_t n_in_tasks = 0;
     int32_t in_split = 256;
+    int64_t max_out_deg = 0, max_in_deg = 0;
     int32_t* dense_u = nullptr;
     int64_t* dense_e0 = nullptr;
     uint32_t* dense_len = nullptr;

@@ -82,6 +82,7 @@ struct SweepDevT {
     dptr<uint32_t, G> act_count;              // [4]
     dptr<uint32_t, G> chg[2];                 // [ceil(n/32)] each
     dptr<uint8_t, G> act8;                    // [flag_bytes(n)] vertex activated for the next sweep; all 0 between sweeps
+    dptr<uint8_t, G> act_blk;                 // [blk_bytes(n)] some vertex of the 1024-vertex block is flagged in act8
     dptr<int32_t, G> chg_list;                // [n_in_tasks]
     dptr<uint32_t, G> chg_count;              // [4]
     dptr<unsigned long long, G> rows_changed; // [4]
@@ -100,6 +101,7 @@ struct CascadeDevT {
     dptr<int32_t, G> q[2];           // frontier out-task lists, capacity ntasks each
     dptr<uint32_t, G> qsize;         // ring of 4 list-size counters
     dptr<uint8_t, G> lv8;            // [flag_bytes(n)] covered at the current level; all 0 between levels
+    dptr<uint8_t, G> lv_blk;         // [blk_bytes(n)] some vertex of the 1024-vertex block is flagged in lv8
     dptr<int32_t, G> touched;        // [n] distinct vertices touched by this cascade
     dptr<uint32_t, G> ntouched;      // counter for `touched`
     dptr<uint32_t, G> touch_stamp;   // [n] id of the last cascade that touched v
@@ -132,6 +134,12 @@ __host__ __device__ inline int pack_rows(int J, int pb)
 
 // Per-vertex flag arrays are padded to whole 16-byte chunks.
 inline int64_t flag_bytes(int64_t n) { return (n + 15) / 16 * 16; }
+// Flag arrays have a summary byte per block of kFlagBlock vertices (set
+// with every flag of the block), so a compaction skips blocks without flags
+// (frontiers of road-like graphs occupy few blocks).
+constexpr int kFlagBlockShift = 10;
+constexpr int kFlagBlock = 1 << kFlagBlockShift;
+inline int64_t blk_bytes(int64_t n) { return flag_bytes((n + kFlagBlock - 1) / kFlagBlock); }
 
 // Event counts of the instrumented propagation kernel (algorithmic traffic).
 struct PropCounters {
@@ -156,7 +164,8 @@ using ArgmaxScratch = ArgmaxScratchT<false>;
 // ---------------------------------------------------------------------------
 // Batched launches.  One launch serves up to kMaxBatch queries: query i owns
 // workgroups wg0[i] .. wg0[i+1]-1 and the argument record args[i] (an array
-// in device memory).
+// in device memory).  A record whose `active` member is 0 makes its
+// workgroups return at once.
 
 constexpr int kMaxBatch = 64;
 
@@ -172,6 +181,7 @@ struct FillArgsT {
     int J;
     int first;  // fresh sketch: every register uncovered
     uint64_t seed;
+    int active = 1;  // 0: this query skips the launch (fixed launch sequences of the engine's graph mode)
 };
 using FillArgs = FillArgsT<false>;
 
@@ -182,6 +192,7 @@ struct PrepArgsT {
     int64_t n;
     int64_t nwords;
     int sweep;
+    int active = 1;  // 0: this query skips the launch (fixed launch sequences of the engine's graph mode)
 };
 using PrepArgs = PrepArgsT<false>;
 
@@ -203,6 +214,7 @@ struct PropArgsT {
     dptr<PropCounters, G> stats;          // instrumented variant only
     dptr<uint32_t, G> vstamp;             // instrumented variant only: [n] last launch id that counted row u
     uint32_t stamp_id;            // instrumented variant only: id of this launch (increasing)
+    int active = 1;  // 0: this query skips the launch (fixed launch sequences of the engine's graph mode)
 };
 using PropArgs = PropArgsT<false>;
 
@@ -212,6 +224,7 @@ struct MarkArgsT {
     SweepDevT<G> s;
     int sweep;
     int dense_div;  // next sweep visits every task when more than n / dense_div rows changed
+    int active = 1;  // 0: this query skips the launch (fixed launch sequences of the engine's graph mode)
 };
 using MarkArgs = MarkArgsT<false>;
 
@@ -222,6 +235,7 @@ struct EstArgsT {
     int J;
     dptr<uint32_t, G> Ju;
     dptr<unsigned long long, G> Hu;
+    int active = 1;  // 0: this query skips the launch (fixed launch sequences of the engine's graph mode)
 };
 using EstArgs = EstArgsT<false>;
 
@@ -234,6 +248,7 @@ struct ArgmaxArgsT {
     ArgmaxScratchT<G> am;
     dptr<int32_t, G> best;
     int nparts;  // workgroups of the partial pass for this query
+    int active = 1;  // 0: this query skips the launch (fixed launch sequences of the engine's graph mode)
 };
 using ArgmaxArgs = ArgmaxArgsT<false>;
 
@@ -252,6 +267,7 @@ struct SeedArgsT {
     dptr<const unsigned long long, G> Hu;
     CascadeDevT<G> c;
     uint32_t cascade_id;
+    int active = 1;  // 0: this query skips the launch (fixed launch sequences of the engine's graph mode)
 };
 using SeedArgs = SeedArgsT<false>;
 
@@ -263,6 +279,7 @@ struct LevelArgsT {
     dptr<uint8_t, G> M;
     CascadeDevT<G> c;
     int t;
+    int active = 1;  // 0: this query skips the launch (fixed launch sequences of the engine's graph mode)
 };
 using LevelArgs = LevelArgsT<false>;
 
@@ -273,6 +290,7 @@ struct LevelCompactArgsT {
     CascadeDevT<G> c;
     int t;                // the level whose flags are compacted into Q_{t+1}
     uint32_t cascade_id;
+    int active = 1;  // 0: this query skips the launch (fixed launch sequences of the engine's graph mode)
 };
 using LevelCompactArgs = LevelCompactArgsT<false>;
 
@@ -283,8 +301,60 @@ struct FinArgsT {
     dptr<uint32_t, G> Ju;
     dptr<unsigned long long, G> Hu;
     CascadeDevT<G> c;
+    int active = 1;  // 0: this query skips the launch (fixed launch sequences of the engine's graph mode)
 };
 using FinArgs = FinArgsT<false>;
+
+// Tail kernels: one workgroup per query runs many sweeps (or cascade levels)
+// in a loop while the frontier stays small, instead of three (or two) grid-wide
+// launches per sweep (level).  The next frontier's distinct vertices are
+// collected in an LDS set, so neither a pass over per-vertex flags nor
+// device-scope atomics are needed.  When the frontier grows past the limits
+// the kernel hands the query back to the full-grid path in a state that path
+// continues from.
+// Why a tail launch stopped: it ran all its rounds (the frontier is still
+// small), the build converged or the cascade ended, or the frontier grew
+// past the limits (handed back).
+constexpr uint32_t kTailStopRounds = 0, kTailStopDone = 1, kTailStopLarge = 2;
+constexpr int kTailCap = 2048;             // distinct vertices of one frontier held in LDS
+constexpr int kTailSlots = 2 * kTailCap;   // LDS set slots
+
+template <bool G>
+struct TailSweepArgsT {
+    GraphDevT<G> g;
+    dptr<const uint32_t, G> X;
+    int J;
+    dptr<uint8_t, G> M;
+    SweepDevT<G> s;
+    dptr<int32_t, G> chg_list2;  // [n_in_tasks] second in-task list; the tail alternates it with s.chg_list
+    dptr<uint32_t, G> next;      // out: the sweep the full-grid path runs next
+    int s0;                      // first sweep; its task list was compacted by the prep step of s0
+    int rounds;                  // sweeps at most
+    int dense_div;               // as for the mark step
+    int64_t arcs_max;            // hand back when the changed rows have more in-arcs than this
+    int64_t tasks_max;           // hand back when the next list has more tasks than this
+    dptr<uint32_t, G> reason;    // out: why the launch stopped (kTailStop*)
+    int active = 1;  // 0: this query skips the launch (fixed launch sequences of the engine's graph mode)
+};
+using TailSweepArgs = TailSweepArgsT<false>;
+
+template <bool G>
+struct TailLevelArgsT {
+    GraphDevT<G> g;
+    dptr<const uint32_t, G> X;
+    int J;
+    dptr<uint8_t, G> M;
+    CascadeDevT<G> c;
+    dptr<uint32_t, G> next;         // out: the level the full-grid path runs next
+    dptr<uint32_t, G> cmp_pending;  // out: level whose flags the compaction must turn into Q_{t+1} (~0u: none)
+    int t0;                         // first level (Q_{t0} built)
+    int rounds;                     // levels at most
+    uint32_t tasks_max;             // hand back frontiers of more tasks than this
+    uint32_t cascade_id;
+    dptr<uint32_t, G> reason;       // out: why the launch stopped (kTailStop*)
+    int active = 1;  // 0: this query skips the launch (fixed launch sequences of the engine's graph mode)
+};
+using TailLevelArgs = TailLevelArgsT<false>;
 
 int device_cu_count();
 int propagate_group_size(int J, int requested);
@@ -305,5 +375,8 @@ hipError_t launch_cascade_seed(const SeedArgs* args, const Batch& B, hipStream_t
 hipError_t launch_cascade_level(const LevelArgs* args, const Batch& B, int maxJ, hipStream_t st);
 hipError_t launch_cascade_compact(const LevelCompactArgs* args, const Batch& B, hipStream_t st);
 hipError_t launch_cascade_finalize(const FinArgs* args, const Batch& B, hipStream_t st);
+// One workgroup per query (B.wg0[i] = i).
+hipError_t launch_tail_sweeps(const TailSweepArgs* args, const Batch& B, int maxJ, hipStream_t st);
+hipError_t launch_tail_levels(const TailLevelArgs* args, const Batch& B, int maxJ, hipStream_t st);
 
 }  // namespace imx

@@ -323,14 +323,18 @@ __device__ __forceinline__ void wg_add_u64(unsigned long long x, unsigned long l
 // Every vertex belongs to one lane, so flags and stamps need no atomics; the
 // lists take one atomic per staged batch.  Wave-uniform control flow.
 template <bool TOUCH>
-__device__ __forceinline__ void compact_flags(uint8_t* flags, int64_t n, const int32_t* task_start, WaveList& L,
-                                              WaveList& T, uint32_t* touch_stamp, uint32_t id, int64_t first_wave,
-                                              int64_t nwaves)
+__device__ __forceinline__ void compact_flags(uint8_t* flags, uint8_t* blk, int64_t n, const int32_t* task_start,
+                                              WaveList& L, WaveList& T, uint32_t* touch_stamp, uint32_t id,
+                                              int64_t first_wave, int64_t nwaves)
 {
+    static_assert(kFlagBlock == 64 * 16, "a wave's 64 chunks of 16 flags are one flag block");
     const int lane = lane_id();
     const int64_t nchunks = (n + 15) / 16;
     uint4* F = reinterpret_cast<uint4*>(flags);
     for (int64_t cb = first_wave * 64; cb < nchunks; cb += nwaves * 64) {
+        // one block of flags per wave iteration; blocks without flags are skipped
+        if (blk[cb >> 6] == 0u) continue;
+        if (lane == 0) blk[cb >> 6] = 0u;
         const int64_t c = cb + lane;
         uint4 f = make_uint4(0u, 0u, 0u, 0u);
         if (c < nchunks) f = F[c];
@@ -426,7 +430,8 @@ __device__ __forceinline__ const S<true>& gview(const S<false>& x)
     const int64_t lb = (int64_t)blockIdx.x - B.wg0[bi_];              \
     const int64_t lg = (int64_t)B.wg0[bi_ + 1] - B.wg0[bi_];          \
     (void)lb;                                                         \
-    (void)lg
+    (void)lg;                                                         \
+    if (!a.active) return
 
 // ---------------------------------------------------------------------------
 // a1: fixed-point thresholds W = min(2^31, floor(p * 2^31)).
@@ -1011,10 +1016,12 @@ int pack_bytes()
 // packs) admits three workgroups per CU, and registers are held to that
 // occupancy's share (measured faster than five waves with more registers, and
 // than seven or eight waves with spills).
+// The body works for workgroup lb of lg workgroups assigned to one query;
+// the single-workgroup tail sweeps call it too.  LDS: pack_lds_words(maxJ,
+// pb, STATS) words from the start of the dynamic area.
 template <bool STATS>
-__global__ __launch_bounds__(kPackWG, 3) void k_propagate_pack(const PropArgs* __restrict__ args, Batch B, int maxJ, int pb)
+__device__ __forceinline__ void propagate_pack_body(const PropArgsT<true>& a, int64_t lb, int64_t lg, int maxJ, int pb)
 {
-    IMX_BATCH_PROLOGUE(PropArgs);
     extern __shared__ uint32_t smem[];
     const int J = a.J;
     const int Jw = J >> 2;
@@ -1352,6 +1359,13 @@ __global__ __launch_bounds__(kPackWG, 3) void k_propagate_pack(const PropArgs* _
     }
 }
 
+template <bool STATS>
+__global__ __launch_bounds__(kPackWG, 3) void k_propagate_pack(const PropArgs* __restrict__ args, Batch B, int maxJ, int pb)
+{
+    IMX_BATCH_PROLOGUE(PropArgs);
+    propagate_pack_body<STATS>(a, lb, lg, maxJ, pb);
+}
+
 // Launch-configuration caches below are shared by every engine of the
 // process; engines may step on different host threads.
 static std::mutex g_launch_cfg_mutex;
@@ -1536,7 +1550,7 @@ __global__ __launch_bounds__(kWG) void k_sweep_prep(const PrepArgs* __restrict__
         __shared__ uint32_t s_flush[kWaves + 1];
         const int wave = (int)(threadIdx.x >> 6);
         WaveList L{wbuf[wave], 0, s.act_tasks[sweep & 1], &s.act_count[sweep & 3]};
-        compact_flags<false>(s.act8, a.n, a.task_start, L, L, nullptr, 0u, lb * kWaves + wave, lg * kWaves);
+        compact_flags<false>(s.act8, s.act_blk, a.n, a.task_start, L, L, nullptr, 0u, lb * kWaves + wave, lg * kWaves);
         wg_flush(L, s_flush);
     }
 }
@@ -1576,7 +1590,11 @@ __global__ __launch_bounds__(kWG) void k_mark(const MarkArgs* __restrict__ args,
         const int64_t e0 = g.in_task_e0[it];
         const int64_t ve = g.in_rowptr[v + 1];
         const int64_t e1 = (e0 + g.in_split < ve) ? e0 + g.in_split : ve;
-        for (int64_t e = e0 + lane; e < e1; e += 64) s.act8[g.in_col[e]] = 1u;
+        for (int64_t e = e0 + lane; e < e1; e += 64) {
+            const int32_t w = g.in_col[e];
+            s.act8[w] = 1u;
+            s.act_blk[w >> kFlagBlockShift] = 1u;
+        }
     }
 }
 
@@ -1845,9 +1863,65 @@ __device__ __forceinline__ int lower_bound_i32(const int* A, int n, int key)
     return lo;
 }
 
-__global__ __launch_bounds__(kWG) void k_cascade_level(const LevelArgs* __restrict__ args, Batch B)
+// Set of vertex ids in LDS for one workgroup (open addressing, linear
+// probing, LDS atomics only): the tail kernels collect the distinct vertices
+// of the next frontier in it.  Slots hold id + 1 (0: empty); the distinct ids
+// are listed in insertion order.  Once `cap` ids are listed, further new ids
+// are not taken and the caller handles them itself (overflow).
+struct LdsSet {
+    uint32_t* slots;     // H words
+    int32_t* list;       // cap entries
+    uint32_t* count;     // distinct ids seen (may exceed cap on overflow)
+    uint32_t* overflow;  // nonzero once an id could not be listed
+    int H;               // a power of two, at least 2 * cap
+    int cap;
+};
+
+// Clears the set (every thread of the workgroup calls it; a barrier follows).
+__device__ __forceinline__ void lds_set_clear(LdsSet& S)
 {
-    IMX_BATCH_PROLOGUE(LevelArgs);
+    for (int i = threadIdx.x; i < S.H; i += blockDim.x) S.slots[i] = 0u;
+    if (threadIdx.x == 0) {
+        *S.count = 0u;
+        *S.overflow = 0u;
+    }
+}
+
+// Adds v; false when v is new but the list is full (the caller keeps v by
+// other means), true otherwise (listed now or before).
+__device__ __forceinline__ bool lds_set_insert(LdsSet& S, int32_t v)
+{
+    const uint32_t key = (uint32_t)v + 1u;
+    uint32_t h = (key * 2654435761u) & (uint32_t)(S.H - 1);
+    for (int probe = 0; probe < S.H; ++probe) {
+        const uint32_t cur = S.slots[h];
+        if (cur == key) return true;
+        if (cur == 0u) {
+            if (__atomic_load_n(S.count, __ATOMIC_RELAXED) >= (uint32_t)S.cap) break;
+            const uint32_t prev = atomicCAS(&S.slots[h], 0u, key);
+            if (prev == 0u) {
+                const uint32_t pos = atomicAdd(S.count, 1u);
+                if (pos < (uint32_t)S.cap) {
+                    S.list[pos] = v;
+                    return true;
+                }
+                break;
+            }
+            if (prev == key) return true;
+        }
+        h = (h + 1u) & (uint32_t)(S.H - 1);
+    }
+    atomicOr(S.overflow, 1u);
+    return false;
+}
+
+// The body works for workgroup lb of lg workgroups assigned to one query.
+// TAIL (the single-workgroup tail kernel): newly covered heads go into the
+// LDS set S instead of the flag array (into the flags only when S is full).
+// NW: waves per workgroup (the per-wave LDS areas follow the table).
+template <bool TAIL, int NW = kWaves>
+__device__ __forceinline__ void cascade_level_body(const LevelArgsT<true>& a, int64_t lb, int64_t lg, LdsSet* S)
+{
     extern __shared__ uint32_t smem[];
     const int J = a.J;
     const int Jw = J >> 2;
@@ -1859,7 +1933,7 @@ __global__ __launch_bounds__(kWG) void k_cascade_level(const LevelArgs* __restri
         a.c.qsize[(a.t + 1) & 3] = 0;  // Q_{t+1}, filled by the compaction
         if (qn == 0u && *a.c.level_end == ~0u) *a.c.level_end = (uint32_t)a.t;
     }
-    if (lb * kWaves >= (int64_t)qn) return;  // no task for this workgroup (uniform)
+    if (lb * NW >= (int64_t)qn) return;  // no task for this workgroup (uniform)
 
     uint32_t* sX = smem;
     const uint32_t* sT = smem + J;
@@ -1872,21 +1946,21 @@ __global__ __launch_bounds__(kWG) void k_cascade_level(const LevelArgs* __restri
     int* epl = reinterpret_cast<int*>(eW + 64);
     int* est = epl + 64;
 
-    for (int i = threadIdx.x; i < J + kBuckets + 1; i += kWG) sX[i] = a.X[i];
+    for (int i = threadIdx.x; i < J + kBuckets + 1; i += 64 * NW) sX[i] = a.X[i];
     __syncthreads();
 
-    const int32_t* Q = a.c.q[a.t & 1];
+    const int32_t* Q = (a.t & 1) ? a.c.q[1] : a.c.q[0];  // a select, not an index: keeps a local record in registers
     uint8_t* lv8 = a.c.lv8;
     const uint32_t mk_prev = marker(a.t - 1);
     const uint32_t mk_cur = marker(a.t);
     const auto& g = a.g;
     const uint32_t* M32 = reinterpret_cast<const uint32_t*>(a.M);
-    const int64_t nw = lg * kWaves;
+    const int64_t nw = lg * NW;
 
     // Task records are loaded one task ahead and task ids two ahead; the
     // first chunk of arcs is loaded with u's row, and every later chunk while
     // the previous one is processed.
-    int64_t i = lb * kWaves + wave;
+    int64_t i = lb * NW + wave;
     int32_t t_nx = (i < (int64_t)qn) ? Q[i] : -1;
     int32_t u_nx = 0;
     int64_t e0_nx = 0;
@@ -1987,7 +2061,10 @@ __global__ __launch_bounds__(kWG) void k_cascade_level(const LevelArgs* __restri
 #pragma unroll
                             for (int b = 0; b < 4; ++b)
                                 if ((m >> (8 * b)) & 1u) p[b] = (uint8_t)mk_cur;
-                            lv8[vk] = 1u;
+                            if (!TAIL || !lds_set_insert(*S, vk)) {
+                                lv8[vk] = 1u;
+                                a.c.lv_blk[vk >> kFlagBlockShift] = 1u;
+                            }
                         }
                     }
                 }
@@ -1997,9 +2074,15 @@ __global__ __launch_bounds__(kWG) void k_cascade_level(const LevelArgs* __restri
     }
 }
 
-static size_t level_lds(int J)
+__global__ __launch_bounds__(kWG) void k_cascade_level(const LevelArgs* __restrict__ args, Batch B)
 {
-    return sizeof(uint32_t) * ((size_t)J + kTableWords + (size_t)kWaves * ((size_t)(J / 2) + kLevelBufWords));
+    IMX_BATCH_PROLOGUE(LevelArgs);
+    cascade_level_body<false>(a, lb, lg, nullptr);
+}
+
+__host__ __device__ static size_t level_lds(int J, int nw = kWaves)
+{
+    return sizeof(uint32_t) * ((size_t)J + kTableWords + (size_t)nw * ((size_t)(J / 2) + kLevelBufWords));
 }
 
 hipError_t cascade_level_full_grid(int maxJ, int* grid)
@@ -2045,7 +2128,8 @@ __global__ __launch_bounds__(kWG) void k_cascade_compact(const LevelCompactArgs*
     WaveList L{wbuf[wave], 0, c.q[(a.t + 1) & 1], &c.qsize[(a.t + 1) & 3]};
     WaveList T{wbuf[wave] + kWaveBufCap, 0, c.touched, c.ntouched};
     __shared__ uint32_t s_flush[kWaves + 1];
-    compact_flags<true>(c.lv8, a.n, a.task_start, L, T, c.touch_stamp, a.cascade_id, lb * kWaves + wave, lg * kWaves);
+    compact_flags<true>(c.lv8, c.lv_blk, a.n, a.task_start, L, T, c.touch_stamp, a.cascade_id, lb * kWaves + wave,
+                        lg * kWaves);
     wg_flush(L, s_flush);
     wg_flush(T, s_flush);
 }
@@ -2135,6 +2219,285 @@ __global__ __launch_bounds__(kWG) void k_cascade_finalize(const FinArgs* __restr
 hipError_t launch_cascade_finalize(const FinArgs* args, const Batch& B, hipStream_t st)
 {
     hipLaunchKernelGGL(k_cascade_finalize, dim3(B.wg0[B.nq]), dim3(kWG), 0, st, args, B);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Tail kernels (one workgroup per query): sweeps or cascade levels of small
+// frontiers in a loop.  Between steps, registers merged by compare-and-swap
+// and changed-bitmap words set by atomics are read by plain loads of other
+// waves; the agent-scope acquire after each barrier invalidates the vector
+// L1 so that those loads see them.
+
+__device__ __forceinline__ void tail_barrier()
+{
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+__device__ __forceinline__ uint32_t ld_u32(const uint32_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long ld_u64(const unsigned long long* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// In-arc range [e0, e1) of in-task it.
+__device__ __forceinline__ void in_task_range(const GraphDevT<true>& g, int32_t it, int64_t& e0, int64_t& e1)
+{
+    const int32_t v = g.in_task_v[it];
+    e0 = g.in_task_e0[it];
+    const int64_t ve = g.in_rowptr[v + 1];
+    e1 = (e0 + g.in_split < ve) ? e0 + g.in_split : ve;
+}
+
+// Sweeps s0, s0+1, ... of one query (Alg. 2), each: propagate over the task
+// list, then (in place of the mark and prep steps) the distinct sources of
+// the in-arcs of the changed rows, collected in the LDS set, give the next
+// list.  Stops when a sweep changes nothing (converged), when the next sweep
+// must visit every task, when the changed rows have more than arcs_max
+// in-arcs (their sources are then flagged as the mark step does), when the
+// next list has more than tasks_max tasks, or after `rounds` sweeps; *next
+// is the sweep the full-grid path runs next (its prep step finds the list,
+// the flags or the dense switch as after its own mark step).
+__global__ __launch_bounds__(kPackWG, 1) void k_tail_sweeps(const TailSweepArgs* __restrict__ args, Batch B, int maxJ,
+                                                            int pb)
+{
+    IMX_BATCH_PROLOGUE(TailSweepArgs);
+    if (lb != 0) return;
+    extern __shared__ uint32_t smem[];
+    __shared__ uint32_t s_cnt, s_ovf, s_pos;
+    __shared__ unsigned long long s_arcs;
+    uint32_t* tl = smem + pack_lds_words(maxJ, pb, false);
+    LdsSet S{tl, reinterpret_cast<int32_t*>(tl + kTailSlots), &s_cnt, &s_ovf, kTailSlots, kTailCap};
+    const auto& g = a.g;
+    const auto& sw = a.s;
+    const int lane = lane_id();
+    const int wave = (int)(threadIdx.x >> 6);
+    uint32_t next = (uint32_t)(a.s0 + a.rounds), why = kTailStopRounds;
+    int s = a.s0;
+    if ((int64_t)ld_u32(&sw.act_count[s & 3]) > a.tasks_max) {  // the first list is too long: hand back at once
+        if (threadIdx.x == 0) {
+            *a.next = (uint32_t)s;
+            *a.reason = kTailStopLarge;
+        }
+        return;
+    }
+    for (int i = 0; i < a.rounds; ++i, ++s) {
+        // in-tasks of the rows changed in sweep s-1 (i = 0: the full-grid
+        // sweep s0-1) and of those changed in sweep s
+        const auto list_in = (i & 1) ? a.chg_list2 : sw.chg_list;
+        const auto list_out = (i & 1) ? sw.chg_list : a.chg_list2;
+        const PropArgsT<true> pa{g,        a.X,      a.J,           a.M,
+                                 sw.act_tasks[s & 1], &sw.act_count[s & 3], sw.chg[s & 1], sw.chg[(s + 1) & 1],
+                                 list_out, &sw.chg_count[s & 3], &sw.dense[s & 3], sw.conv,
+                                 &sw.rows_changed[s & 3], nullptr, nullptr, 0u};
+        propagate_pack_body<false>(pa, 0, 1, maxJ, pb);
+        tail_barrier();
+        const unsigned long long changed = ld_u64(&sw.rows_changed[s & 3]);
+        if (changed == 0ull) {  // converged at sweep s
+            if (threadIdx.x == 0) *sw.conv = (uint32_t)s;
+            next = (uint32_t)s + 1u;
+            why = kTailStopDone;
+            break;
+        }
+        const bool dense = changed * (unsigned long long)a.dense_div > (unsigned long long)g.n;
+        if (threadIdx.x == 0) {
+            sw.dense[(s + 1) & 3] = dense ? 1u : 0u;
+            sw.act_count[(s + 1) & 3] = 0u;
+            s_arcs = 0ull;
+            s_pos = 0u;
+        }
+        if (dense) {
+            next = (uint32_t)s + 1u;
+            why = kTailStopLarge;
+            break;
+        }
+        const uint32_t nin = ld_u32(&sw.chg_count[s & 3]);
+        lds_set_clear(S);
+        __syncthreads();
+        // in-arcs of the changed rows
+        unsigned long long na = 0;
+        for (uint32_t q = threadIdx.x; q < nin; q += blockDim.x) {
+            int64_t e0, e1;
+            in_task_range(g, list_out[q], e0, e1);
+            na += (unsigned long long)(e1 - e0);
+        }
+        na = wave_sum_u64(na);
+        if (lane == 0 && na) atomicAdd(&s_arcs, na);
+        __syncthreads();
+        const bool flag = s_arcs > (unsigned long long)a.arcs_max;
+        for (uint32_t q = wave; q < nin; q += kPackWaves) {
+            int64_t e0, e1;
+            in_task_range(g, list_out[q], e0, e1);
+            for (int64_t e = e0 + lane; e < e1; e += 64) {
+                const int32_t w = g.in_col[e];
+                if (flag || !lds_set_insert(S, w)) {
+                    sw.act8[w] = 1u;
+                    sw.act_blk[w >> kFlagBlockShift] = 1u;
+                }
+            }
+        }
+        __syncthreads();
+        if (flag || s_ovf) {  // the prep step of sweep s+1 compacts the flags
+            for (uint32_t k = threadIdx.x; k < min(s_cnt, (uint32_t)kTailCap); k += blockDim.x) {
+                sw.act8[S.list[k]] = 1u;
+                sw.act_blk[S.list[k] >> kFlagBlockShift] = 1u;
+            }
+            next = (uint32_t)s + 1u;
+            why = kTailStopLarge;
+            break;
+        }
+        // the list of sweep s+1: the out-tasks of the distinct sources
+        const auto out = sw.act_tasks[(s + 1) & 1];
+        for (uint32_t k = threadIdx.x; k < s_cnt; k += blockDim.x) {
+            const int32_t w = S.list[k];
+            const int32_t t0 = g.task_start[w], cnt = g.task_start[w + 1] - t0;
+            const uint32_t pos = atomicAdd(&s_pos, (uint32_t)cnt);
+            for (int q = 0; q < cnt; ++q) out[pos + q] = t0 + q;
+        }
+        // clear the changed bits of sweep s-1 (read by this sweep) for reuse by
+        // sweep s+1: the rows with in-arcs are those of list_in; bits of rows
+        // without in-arcs are never read and only ever set again
+        const uint32_t nprev = ld_u32(&sw.chg_count[(s - 1) & 3]);
+        for (uint32_t q = threadIdx.x; q < nprev; q += blockDim.x) {
+            const int32_t v = g.in_task_v[list_in[q]];
+            sw.chg[s & 1][(uint32_t)v >> 5] = 0u;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            sw.act_count[(s + 1) & 3] = s_pos;
+            sw.rows_changed[(s + 1) & 3] = 0ull;
+            sw.chg_count[(s + 1) & 3] = 0u;
+        }
+        const bool stop = (int64_t)s_pos > a.tasks_max;
+        tail_barrier();
+        if (stop) {
+            next = (uint32_t)s + 1u;
+            why = kTailStopLarge;
+            break;
+        }
+    }
+    if (threadIdx.x == 0) {
+        *a.next = next;
+        *a.reason = why;
+    }
+}
+
+// Levels t0, t0+1, ... of one cascade (Alg. 3): each expands Q_t; the
+// distinct newly covered heads, collected in the LDS set, give Q_{t+1} (their
+// out-tasks) and join the touched list once per cascade.  Stops at an empty
+// frontier (the cascade is over: level_end), before a frontier of more than
+// tasks_max tasks, when the LDS set fills up (the heads of level t are then
+// flagged and *cmp_pending = t: the compaction of level t must run before
+// level t+1), or after `rounds` levels; *next is the level the full-grid
+// path runs next.
+constexpr int kTailLevelWaves = 8;
+
+__global__ __launch_bounds__(64 * kTailLevelWaves, 1) void k_tail_levels(const TailLevelArgs* __restrict__ args, Batch B,
+                                                                         int maxJ)
+{
+    IMX_BATCH_PROLOGUE(TailLevelArgs);
+    if (lb != 0) return;
+    extern __shared__ uint32_t smem[];
+    __shared__ uint32_t s_cnt, s_ovf, s_pos, s_tpos;
+    uint32_t* tl = smem + level_lds(maxJ, kTailLevelWaves) / sizeof(uint32_t);
+    LdsSet S{tl, reinterpret_cast<int32_t*>(tl + kTailSlots), &s_cnt, &s_ovf, kTailSlots, kTailCap};
+    const auto& g = a.g;
+    const auto& c = a.c;
+    uint32_t next = (uint32_t)(a.t0 + a.rounds), pending = ~0u, why = kTailStopRounds;
+    int t = a.t0;
+    for (int i = 0; i < a.rounds; ++i, ++t) {
+        const uint32_t qn = ld_u32(&c.qsize[t & 3]);
+        if (qn == 0u) {  // empty frontier: the cascade ended at level t
+            if (threadIdx.x == 0 && *c.level_end == ~0u) *c.level_end = (uint32_t)t;
+            next = (uint32_t)t;
+            why = kTailStopDone;
+            break;
+        }
+        if (qn > a.tasks_max) {
+            next = (uint32_t)t;
+            why = kTailStopLarge;
+            break;
+        }
+        lds_set_clear(S);
+        if (threadIdx.x == 0) {
+            s_pos = 0u;
+            s_tpos = 0u;
+        }
+        __syncthreads();
+        const LevelArgsT<true> la{g, a.X, a.J, a.M, c, t};
+        cascade_level_body<true, kTailLevelWaves>(la, 0, 1, &S);
+        tail_barrier();
+        if (s_ovf) {  // heads beyond the set were flagged; flag the listed ones too
+            for (uint32_t k = threadIdx.x; k < min(s_cnt, (uint32_t)kTailCap); k += blockDim.x) {
+                c.lv8[S.list[k]] = 1u;
+                c.lv_blk[S.list[k] >> kFlagBlockShift] = 1u;
+            }
+            pending = (uint32_t)t;
+            next = (uint32_t)t + 1u;
+            why = kTailStopLarge;
+            break;
+        }
+        const uint32_t base_t = ld_u32(c.ntouched);
+        const auto out = ((t + 1) & 1) ? c.q[1] : c.q[0];
+        for (uint32_t k = threadIdx.x; k < s_cnt; k += blockDim.x) {
+            const int32_t v = S.list[k];
+            const int32_t t0 = g.task_start[v], cnt = g.task_start[v + 1] - t0;
+            const uint32_t pos = atomicAdd(&s_pos, (uint32_t)cnt);
+            for (int q = 0; q < cnt; ++q) out[pos + q] = t0 + q;
+            if (c.touch_stamp[v] != a.cascade_id) {
+                c.touch_stamp[v] = a.cascade_id;
+                c.touched[base_t + atomicAdd(&s_tpos, 1u)] = v;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            c.qsize[(t + 1) & 3] = s_pos;
+            *c.ntouched = base_t + s_tpos;
+        }
+        tail_barrier();
+    }
+    if (threadIdx.x == 0) {
+        *a.next = next;
+        *a.cmp_pending = pending;
+        *a.reason = why;
+    }
+}
+
+template <class K>
+static hipError_t tail_setup(K kernel, size_t lds, size_t* attr_set)
+{
+    std::lock_guard<std::mutex> lock(g_launch_cfg_mutex);
+    if (lds > *attr_set) {
+        hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (err != hipSuccess) return err;
+        *attr_set = lds;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_tail_sweeps(const TailSweepArgs* args, const Batch& B, int maxJ, hipStream_t st)
+{
+    static size_t attr_set = 0;
+    const int pb = pack_bytes();
+    const size_t lds = sizeof(uint32_t) * ((size_t)pack_lds_words(maxJ, pb, false) + kTailSlots + kTailCap);
+    hipError_t err = tail_setup(&k_tail_sweeps, lds, &attr_set);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k_tail_sweeps, dim3(B.wg0[B.nq]), dim3(kPackWG), lds, st, args, B, maxJ, pb);
+    return hipGetLastError();
+}
+
+hipError_t launch_tail_levels(const TailLevelArgs* args, const Batch& B, int maxJ, hipStream_t st)
+{
+    static size_t attr_set = 0;
+    const size_t lds = level_lds(maxJ, kTailLevelWaves) + sizeof(uint32_t) * ((size_t)kTailSlots + kTailCap);
+    hipError_t err = tail_setup(&k_tail_levels, lds, &attr_set);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k_tail_levels, dim3(B.wg0[B.nq]), dim3(64 * kTailLevelWaves), lds, st, args, B, maxJ);
     return hipGetLastError();
 }
 

@@ -134,6 +134,8 @@ size_t carve(uint8_t* base, const im_graph* g, int J, int K, NaBuffers* b)
     b->seeds = C.take<int32_t>((size_t)K);
     b->pickJ = C.take<uint32_t>((size_t)K);
     b->pickH = C.take<unsigned long long>((size_t)K);
+    b->sw.act_blk = C.take<uint8_t>((size_t)blk_bytes((int64_t)n));
+    b->c.lv_blk = C.take<uint8_t>((size_t)blk_bytes((int64_t)n));
     if (base) {
         NaStatus* S = b->status;
         b->sw.rows_changed = S->rows_changed;
@@ -351,6 +353,8 @@ im_status im_select_seeds_noalloc(const im_graph* g, int32_t J, uint64_t seed, i
     IMX_HIP(hipMemsetAsync(R.b.sw.act8, 0, (size_t)flag_bytes(g->n), R.st));
     IMX_HIP(hipMemsetAsync(R.b.c.lv8, 0, (size_t)flag_bytes(g->n), R.st));
     IMX_HIP(hipMemsetAsync(R.b.c.touch_stamp, 0, sizeof(uint32_t) * (size_t)g->n, R.st));
+    IMX_HIP(hipMemsetAsync(R.b.sw.act_blk, 0, (size_t)blk_bytes(g->n), R.st));
+    IMX_HIP(hipMemsetAsync(R.b.c.lv_blk, 0, (size_t)blk_bytes(g->n), R.st));
     IMX_HIP(launch_sim_values(seed, J, R.b.X, R.st));
 
     int sweeps = 0;

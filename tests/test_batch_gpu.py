@@ -208,3 +208,49 @@ def test_engine_graph_mode_equals_solo(imx):
     for i, r in enumerate(solo):
         _same(got[i], r)
     E.free()
+
+
+def test_engine_graph_mode_replays_fixed_sequence(imx, orc):
+    """Graph mode on an uneven mix (RMAT and Barabasi-Albert graphs of
+    different sizes, different J and K): every step launches every kernel kind
+    for every running query (inactive records return at once), so the launch
+    sequence changes only when a query finishes and its captured graph
+    replays in between.  Results equal the solo runs and the oracle."""
+    specs = [("rmat", 9, 0), ("rmat", 11, 1), ("ba", 1500, 2), ("rmat", 10, 3), ("ba", 4000, 4), ("rmat", 12, 5),
+             ("ba", 800, 6), ("rmat", 8, 7)]
+    cases = []
+    for kind, size, i in specs:
+        g = graphgen.rmat(size, 16, seed=50 + i) if kind == "rmat" else graphgen.barabasi_albert(size, 8, seed=i)
+        cases.append((graphgen.with_p(g, "wc"), (64, 128, 256)[i % 3], 20 + i, 4 + (i % 5)))
+    Gs = [imx.Graph.from_graphgen(g) for g, *_ in cases]
+    solo = [_solo(imx, G, J, s, K) for G, (_, J, s, K) in zip(Gs, cases)]
+    for (g, J, s, K), r in zip(cases, solo):
+        _same_as_oracle(r, orc.greedy(g, J, s, K, keep_registers=False))
+    E = imx.Engine(max_queries=len(cases))
+    E.set_tuning(use_graphs=1, rounds_per_step=4)
+    ids = [E.submit(G, J, s, K) for G, (_, J, s, K) in zip(Gs, cases)]
+    res = E.run()
+    c = E.counters()
+    _say(f"[graph replay] {c}")
+    for qid, r in zip(ids, solo):
+        _same(res[qid], r)
+    # one structure per set of running queries: at most one per finished query
+    assert c["graphs_built"] <= len(cases) + 1, c
+    assert c["graph_replays"] >= 4 * c["graphs_built"], c
+    E.free()
+
+
+def test_engine_graph_mode_two_kernel_choices(imx):
+    """Graph mode with different propagation kernels for the first and later
+    sweeps (two propagation records per query and round) and the most rounds
+    per step: every record of a step fits the step's argument buffer."""
+    cases = _graphs()
+    Gs = [imx.Graph.from_graphgen(g) for g, *_ in cases]
+    solo = [_solo(imx, G, J, s, K) for G, (_, J, s, K) in zip(Gs, cases)]
+    E = imx.Engine(max_queries=len(cases))
+    E.set_tuning(use_graphs=1, rounds_per_step=16, group_first=64, group_rest=0)
+    ids = [E.submit(G, J, s, K) for G, (_, J, s, K) in zip(Gs, cases)]
+    res = E.run()
+    for qid, r in zip(ids, solo):
+        _same(res[qid], r)
+    E.free()

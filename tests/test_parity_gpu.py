@@ -115,6 +115,35 @@ def test_lane_group_kernels_with_oracle(imx, orc, monkeypatch, name, groups):
     assert_parity(orc, gpu, ref, J, seed)
 
 
+# Tail kernels (one workgroup per query runs many sweeps or cascade levels of
+# a small frontier): forced for every frontier (limits huge, two rounds per
+# launch so that launches hand over to each other), with tiny limits (frequent
+# hand-backs to the full-grid path), and switched off.  A dense ER graph makes
+# frontiers overflow the LDS set (flag hand-backs).
+TAIL_SETTINGS = {
+    "forced": {"IMX_TAIL": "1", "IMX_TAIL_ROWS": "1000000000", "IMX_TAIL_TASKS": "1000000000", "IMX_TAIL_ROUNDS": "2"},
+    "tiny": {"IMX_TAIL": "1", "IMX_TAIL_ROWS": "4", "IMX_TAIL_TASKS": "3", "IMX_TAIL_ROUNDS": "3"},
+    "off": {"IMX_TAIL": "0"},
+}
+TAIL_CASES = dict(CASES)
+TAIL_CASES["er6000_p0.5_J64"] = (lambda: graphgen.with_p(graphgen.erdos_renyi(6000, 60000, 11), "0.5"), 64, 19, 4)
+TAIL_CASE_NAMES = ["c1_er1k_p0.1_J64_s1", "er400_wc_J128", "er300_tri_J192", "er150_p0.3_J4096", "hub2000_p0.2_J256",
+                   "rmat12_wc_J512", "ba3000_wc_J256", "cycle50_p1_J64", "er60_p1_J128_Kn", "er6000_p0.5_J64"]
+
+
+@pytest.mark.parametrize("setting", list(TAIL_SETTINGS))
+@pytest.mark.parametrize("name", TAIL_CASE_NAMES)
+def test_tail_kernels_with_oracle(imx, orc, monkeypatch, name, setting):
+    make, J, seed, K = TAIL_CASES[name]
+    g = make()
+    for k, v in TAIL_SETTINGS[setting].items():
+        monkeypatch.setenv(k, v)
+    _say(f"[tail {setting}] {name}")
+    ref = orc.greedy(g, J, seed, K)
+    gpu = run_gpu(imx, g, J, seed, K)
+    assert_parity(orc, gpu, ref, J, seed)
+
+
 @pytest.mark.parametrize("n,K", [(1, 1), (10, 10)])
 def test_edgeless_graphs(imx, orc, n, K):
     g = graphgen.Graph(n=n, rowptr=np.zeros(n + 1, np.int64), col=np.zeros(0, np.int32),
