@@ -276,7 +276,17 @@ def served_main(args):
     """Poisson stream of IM queries over device-resident graphs (RMAT scales
     given by --served-scales, edge factor 16, two p-schemes each), J in
     {128, 512}, K uniform in [10, 100]: continuous batching against a serial
-    one-query-at-a-time server on the same trace."""
+    one-query-at-a-time server.
+
+    The serial server is measured once per query: every query runs alone,
+    back to back, through a one-slot server (submit to result), which gives its
+    service time and its outputs.  A FIFO single server is work-conserving, so
+    its latencies on any arrival trace follow exactly from those service times
+    (start = max(arrival, previous finish)).  Continuous batching is replayed
+    in real time on the trace of each load level; its outputs must equal the
+    serial ones query by query.  --served-service-out / --served-service-in
+    save and reuse the serial pass, so the load levels of a long run can be
+    replayed in separate processes."""
     import numpy as np
     import torch
 
@@ -300,40 +310,59 @@ def served_main(args):
     reqs = [(names[int(rng.integers(len(names)))], int(rng.choice([128, 512])), int(i),
              int(rng.integers(10, 101))) for i in range(nq)]
 
-    def serial_time(sample):
-        t = time.perf_counter()
-        for (gname, J, s, K) in sample:
-            S = imx.Sketch(graphs[gname], J, s, stream=stream)
-            S.select(K)
-            S.free()
-        return (time.perf_counter() - t) / len(sample)
-
-    svc = serial_time(reqs[: max(4, nq // 8)])
+    if args.served_service_in:
+        sv = json.load(open(args.served_service_in))
+        assert sv["queries"] == nq and sv["scales"] == args.served_scales, "service file of another workload"
+        service, serial_out = sv["service_s"], sv["outputs"]
+    else:
+        srv = serve.Server(graphs, max_queries=1, stream=stream).start()
+        service, serial_out = [], []
+        for i, (gname, J, s, K) in enumerate(reqs):
+            r = srv.submit(gname, J, s, K).result()
+            service.append(r["latency_s"])
+            serial_out.append({"seeds": [int(x) for x in r["seeds"]], "T": [int(x) for x in r["T"]]})
+            if i % 50 == 0:
+                print(f"[bench] serial pass {i}/{nq}: {sum(service):.1f} s", file=sys.stderr, flush=True)
+        srv.stop()
+        if args.served_service_out:
+            json.dump({"queries": nq, "scales": args.served_scales, "service_s": service, "outputs": serial_out},
+                      open(args.served_service_out, "w"))
+    svc = float(np.mean(service))
+    # the trace of each load level: arrivals from their own seeded stream
     out = {"metric": "served IM queries: throughput and p50/p99 latency",
            "unit": "queries/s", "n_gpus": 1, "mean_serial_service_s": svc, "levels": []}
+    slots = [int(x) for x in args.served_slots.split(",")]
+    lanes = [int(x) << 20 for x in args.served_lanes_mib.split(",")]
+    caps = [int(x) for x in args.served_caps.split(",")]
+    tunings = [dict(grid_cap=c) for c in caps]
     for load in [float(x) for x in args.served_loads.split(",")]:
         lam = load / svc
-        arr = np.cumsum(rng.exponential(1.0 / lam, size=nq))
+        arr = np.cumsum(np.random.Generator(np.random.PCG64(int(round(load * 1000)))).exponential(1.0 / lam, size=nq))
         trace = [(float(t), *r) for t, r in zip(arr, reqs)]
-        row = {"load": load, "lambda_qps": lam}
-        slots = [int(x) for x in args.served_slots.split(",")]
-        for mode, mq in (("continuous_batching", slots), ("serial", 1)):
-            lanes = [int(x) << 20 for x in args.served_lanes_mib.split(",")] if mode != "serial" else None
-            srv = serve.Server(graphs, max_queries=mq, stream=stream, lanes=lanes).start()
-            res, span = serve.replay(srv, trace)
-            srv.stop()
-            row[mode] = serve.latency_summary(res, span)
-            row[mode + "_results"] = res
-            print(f"[bench] load {load} {mode}: {row[mode]}", file=sys.stderr, flush=True)
-        a, b = row.pop("continuous_batching_results"), row.pop("serial_results")
-        for ra, rb in zip(a, b):
-            assert list(ra["seeds"]) == list(rb["seeds"]) and list(ra["T"]) == list(rb["T"]), "outputs differ"
+        # serial: FIFO single server on the measured service times
+        fin, lat = 0.0, []
+        for ta, st in zip(arr, service):
+            fin = max(fin, ta) + st
+            lat.append(fin - ta)
+        lat = np.array(lat) * 1e3
+        row = {"load": load, "lambda_qps": lam,
+               "serial": {"queries": nq, "throughput_qps": nq / fin, "p50_ms": float(np.percentile(lat, 50)),
+                          "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()), "makespan_s": fin}}
+        srv = serve.Server(graphs, max_queries=slots, stream=stream, lanes=lanes, tuning=tunings).start()
+        res, span = serve.replay(srv, trace)
+        srv.stop()
+        row["continuous_batching"] = serve.latency_summary(res, span)
+        for r, ref in zip(res, serial_out):
+            assert [int(x) for x in r["seeds"]] == ref["seeds"] and [int(x) for x in r["T"]] == ref["T"], \
+                "outputs differ"
         row["identical_outputs"] = True
+        print(f"[bench] load {load}: serial {row['serial']} | continuous batching {row['continuous_batching']}",
+              file=sys.stderr, flush=True)
         out["levels"].append(row)
     out["value"] = max(r["continuous_batching"]["throughput_qps"] for r in out["levels"])
     out["config"] = {"workload": "served_rmat" + "-".join(map(str, scales)) + "_p0.01+wc_J128|512_K10-100",
                      "queries_per_level": nq, "slots_per_lane": args.served_slots,
-                     "lanes_mib": args.served_lanes_mib}
+                     "lanes_mib": args.served_lanes_mib, "lane_grid_caps": args.served_caps}
     print(json.dumps(out), flush=True)
 
 
@@ -421,6 +450,10 @@ def main():
     ap.add_argument("--served-queries", type=int, default=64)
     ap.add_argument("--served-loads", default="0.5,0.8,1.0")
     ap.add_argument("--served-slots", default="16,8,1", help="queries each lane holds at once")
+    ap.add_argument("--served-caps", default="0,0,0",
+                    help="workgroup cap of every launch of each lane's engine (0: none)")
+    ap.add_argument("--served-service-out", default="", help="write the serial pass (service times, outputs) here")
+    ap.add_argument("--served-service-in", default="", help="reuse a serial pass written by --served-service-out")
     ap.add_argument("--served-lanes-mib", default="128,1024",
                     help="footprint bounds (MiB) of the serving lanes; larger queries take the last lane")
     ap.add_argument("--gather-calibration", type=int, default=0, metavar="MIB",

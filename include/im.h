@@ -284,14 +284,25 @@ im_status im_engine_create(int32_t max_queries, uint64_t hbm_budget_bytes, void*
  *   dense_div                a sweep visits every task instead of an active
  *                            list when more than n / dense_div rows changed in
  *                            the previous sweep (>= 1);
- *   use_graphs               1: a step's launches are captured in a HIP graph
- *                            the first time their structure (kernels, grids,
- *                            query split) occurs and replayed while it repeats
- *                            (no per-launch kernel times then); 0: direct
- *                            launches.
- * Defaults: 0, 0, 8, 16, 0; the environment variables IMX_GROUP_FIRST,
- * IMX_GROUP, IMX_ROUNDS, IMX_DENSE_DIV and IMX_GRAPHS override them at engine
- * creation (an out-of-range value makes creation fail with IM_EINVAL).
+ *   use_graphs               1: every step launches every kernel kind for
+ *                            every running query (records of queries in
+ *                            other stages are inactive), so the launch
+ *                            sequence changes only when a query is admitted
+ *                            or finishes; it is captured in a HIP graph the
+ *                            first time it occurs and replayed while it
+ *                            repeats (no per-launch kernel times then);
+ *                            0: direct launches of the queries in each stage;
+ *   grid_cap                 at most this many workgroups in any launch of
+ *                            the engine (0: no cap), e.g. to keep an engine of
+ *                            small queries from crowding out another engine's
+ *                            large ones on a shared device;
+ *   tails                    single-workgroup tail kernels for small
+ *                            frontiers (many sweeps or cascade levels in one
+ *                            launch): 0 off, 1 on, 2 only for graphs whose
+ *                            largest in- and out-degree is at most 64.
+ * Defaults: 0, 0, 8, 16, 0, 0, 2; the environment variables IMX_GROUP_FIRST,
+ * IMX_GROUP, IMX_ROUNDS, IMX_DENSE_DIV, IMX_GRAPHS and IMX_TAIL override them at
+ * engine creation (an out-of-range value makes creation fail with IM_EINVAL).
  * IMX_PROP_GRID (>= 1), read at engine creation, caps the workgroups of a
  * propagation launch (a test of schedule independence; never faster). */
 typedef struct im_tuning {
@@ -300,6 +311,8 @@ typedef struct im_tuning {
     int32_t rounds_per_step;
     int32_t dense_div;
     int32_t use_graphs;
+    int32_t grid_cap;
+    int32_t tails;
 } im_tuning;
 
 im_status im_engine_set_tuning(im_engine* e, const im_tuning* t);

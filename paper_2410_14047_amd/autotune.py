@@ -15,7 +15,7 @@ from typing import Iterable, Optional
 
 from .binding import Engine, Graph
 
-DEFAULT = dict(group_first=0, group_rest=0, rounds_per_step=8, dense_div=16, use_graphs=0)
+DEFAULT = dict(group_first=0, group_rest=0, rounds_per_step=8, dense_div=16, use_graphs=0, grid_cap=0, tails=2)
 
 
 def candidate_grid(J_max: int) -> list:

@@ -367,7 +367,7 @@ class Sketch:
 class im_tuning(ctypes.Structure):
     _fields_ = [("group_first", ctypes.c_int32), ("group_rest", ctypes.c_int32),
                 ("rounds_per_step", ctypes.c_int32), ("dense_div", ctypes.c_int32),
-                ("use_graphs", ctypes.c_int32)]
+                ("use_graphs", ctypes.c_int32), ("grid_cap", ctypes.c_int32), ("tails", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -419,8 +419,8 @@ class Engine:
         return dict(seeds=seeds, spread=spread.value, est=est, T=T, stats=stats.as_dict())
 
     def set_tuning(self, group_first: int = 0, group_rest: int = 0, rounds_per_step: int = 8,
-                   dense_div: int = 16, use_graphs: int = 0) -> None:
-        t = im_tuning(group_first, group_rest, rounds_per_step, dense_div, int(use_graphs))
+                   dense_div: int = 16, use_graphs: int = 0, grid_cap: int = 0, tails: int = 2) -> None:
+        t = im_tuning(group_first, group_rest, rounds_per_step, dense_div, int(use_graphs), grid_cap, tails)
         _check(lib().im_engine_set_tuning(self.handle, ctypes.byref(t)))
 
     def get_tuning(self) -> dict:

@@ -177,12 +177,12 @@ public:
         if (const char* v = std::getenv("IMX_ROUNDS")) t.rounds_per_step = std::atoi(v);
         if (const char* v = std::getenv("IMX_DENSE_DIV")) t.dense_div = std::atoi(v);
         if (const char* v = std::getenv("IMX_GRAPHS")) t.use_graphs = std::atoi(v);
+        if (const char* v = std::getenv("IMX_TAIL")) t.tails = std::atoi(v);
         if (set_tuning(t) != IM_OK) return IM_EINVAL;
         // Cap on the workgroups of a propagation launch (schedule tests: few
         // workgroups make every one of them take many packs).
         // Tail kernels for small frontiers (on unless IMX_TAIL=0; limits by
         // environment for experiments).
-        if (const char* v = std::getenv("IMX_TAIL")) tail_mode_ = std::atoi(v);
         if (const char* v = std::getenv("IMX_TAIL_ROWS")) tail_rows_ = std::max(0, std::atoi(v));
         if (const char* v = std::getenv("IMX_TAIL_TASKS")) tail_tasks_ = std::max(1, std::atoi(v));
         if (const char* v = std::getenv("IMX_TAIL_ROUNDS")) tail_rounds_ = std::max(1, std::atoi(v));
@@ -293,7 +293,8 @@ public:
         }
         q->stage = Stage::Fill;
         q->fresh = true;
-        q->tails_ok = tail_mode_ == 1 || (tail_mode_ == 2 && std::max(g->max_out_deg, g->max_in_deg) <= kTailAutoDegree);
+        q->tails_ok = tune_.tails == 1 ||
+                      (tune_.tails == 2 && std::max(g->max_out_deg, g->max_in_deg) <= kTailAutoDegree);
         q->t_build0 = now_ms();
         used_ += A.bytes;
         slots_[slot] = q.get();
@@ -411,7 +412,8 @@ public:
     {
         auto ok_gs = [](int v) { return v == 0 || v == 16 || v == 32 || v == 64; };
         if (!ok_gs(t.group_first) || !ok_gs(t.group_rest) || t.rounds_per_step < 1 ||
-            t.rounds_per_step > kMaxRounds || t.dense_div < 1 || (t.use_graphs != 0 && t.use_graphs != 1))
+            t.rounds_per_step > kMaxRounds || t.dense_div < 1 || (t.use_graphs != 0 && t.use_graphs != 1) ||
+            t.grid_cap < 0 || t.tails < 0 || t.tails > 2)
             return set_error(IM_EINVAL, "tuning out of range");
         tune_ = t;
         return IM_OK;
@@ -474,10 +476,9 @@ private:
     // (or whose next level has at most tail_tasks_ tasks, or a new cascade)
     // runs up to tail_rounds_ sweeps (levels) in one single-workgroup launch;
     // the kernels hand back frontiers beyond tail_tasks_ tasks.
-    // 0 off, 1 on, 2 (default) for graphs of bounded degree only: with hubs
+    // Tail mode 2 (default) serves graphs of bounded degree only: with hubs
     // (power-law graphs) a few changed rows have thousands of in-arcs, so
     // small frontiers rarely stay small for a single workgroup.
-    int tail_mode_ = 2;
     static constexpr int64_t kTailAutoDegree = 64;
     int tail_rows_ = 64, tail_tasks_ = 64, tail_rounds_ = 256;
     size_t used_ = 0;
@@ -512,7 +513,7 @@ private:
         }
         graphs_.clear();
     }
-    im_tuning tune_{0, 0, 8, 16, 0};
+    im_tuning tune_{0, 0, 8, 16, 0, 0, 2};
 };
 
 im_status Engine::step()
@@ -539,7 +540,7 @@ im_status Engine::step()
     const bool stats = profiling_level() >= 2;
     // Small frontiers go to the tail kernels (not in instrumented runs, whose
     // counters cover the full-grid propagation kernel only).
-    const bool tails = tail_mode_ != 0 && !stats;
+    const bool tails = tune_.tails != 0 && !stats;
     std::vector<Query*> fill_q, sweep_q, est_q, pick_q, level_q, tailsw_q, taillv_q, cmp_q;
     for (Query* q : act) q->tail_kind = 0;
     for (Query* q : act) {
@@ -798,6 +799,8 @@ im_status Engine::step()
     std::vector<int64_t> key;
     auto finish = [&](int kind, auto& L, int64_t cap) -> bool {
         L.dev = stage_args(L.args);
+        if (tune_.grid_cap > 0 && kind != 6)  // the partial argmax keeps its per-query partial count
+            cap = cap > 0 ? std::min<int64_t>(cap, tune_.grid_cap) : tune_.grid_cap;
         L.B = make_batch(L.want, cap);
         key.push_back(kind);
         key.push_back(L.dev ? reinterpret_cast<const uint8_t*>(L.dev) - args_dev_ : -1);

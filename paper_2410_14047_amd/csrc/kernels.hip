@@ -1739,20 +1739,27 @@ __device__ void block_reduce_best(Cand& c)
     c = Cand{sJ[0], sH[0], sI[0]};
 }
 
+// Partial b (0 <= b < nparts) covers the vertices v with (v / 256) % nparts
+// == b.  Workgroup lb of the query's lg computes partials lb, lb + lg, ..., so
+// every one of the nparts slots the final pass reads is written whatever the
+// grid (a capped grid gives fewer workgroups than partials).
 __global__ __launch_bounds__(256) void k_argmax_partial(const ArgmaxArgs* __restrict__ args, Batch B)
 {
     IMX_BATCH_PROLOGUE(ArgmaxArgs);
-    Cand best{0u, 0ull, -1};
-    for (int64_t v = lb * blockDim.x + threadIdx.x; v < a.n; v += lg * blockDim.x) {
-        if (a.is_seed[v]) continue;
-        Cand c{a.Ju[v], a.Hu[v], (int32_t)v};
-        if (better(c, best)) best = c;
-    }
-    block_reduce_best(best);
-    if (threadIdx.x == 0) {
-        a.am.pJ[lb] = best.J;
-        a.am.pH[lb] = best.H;
-        a.am.pid[lb] = best.id;
+    for (int64_t b = lb; b < a.nparts; b += lg) {
+        Cand best{0u, 0ull, -1};
+        for (int64_t v = b * blockDim.x + threadIdx.x; v < a.n; v += (int64_t)a.nparts * blockDim.x) {
+            if (a.is_seed[v]) continue;
+            Cand c{a.Ju[v], a.Hu[v], (int32_t)v};
+            if (better(c, best)) best = c;
+        }
+        block_reduce_best(best);
+        if (threadIdx.x == 0) {
+            a.am.pJ[b] = best.J;
+            a.am.pH[b] = best.H;
+            a.am.pid[b] = best.id;
+        }
+        __syncthreads();  // block_reduce_best's LDS is reused by the next partial
     }
 }
 
@@ -1792,7 +1799,7 @@ __global__ __launch_bounds__(64) void k_cascade_seed(const SeedArgs* __restrict_
     const auto& c = a.c;
     const int lane = lane_id();
     const int32_t s = *a.best;
-    if (s < 0) {  // no candidate (cannot happen for K <= n); leave an empty cascade
+    if (s < 0 || (int64_t)s >= g.n) {  // no candidate (cannot happen for K <= n); leave an empty cascade
         if (lane == 0) {
             a.seeds[a.k] = -1;
             c.qsize[0] = c.qsize[1] = c.qsize[2] = c.qsize[3] = 0;

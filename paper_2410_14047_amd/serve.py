@@ -94,8 +94,11 @@ class Server:
     to the last lane otherwise (None: one lane).  max_queries (one value, or one per lane)
     and hbm_budget_bytes apply per lane; a lane of large queries with one slot
     serves them first come, first served while the other lanes interleave
-    small ones.  `streams` (optional) gives each lane's stream; by default a
-    new torch stream per lane, or `stream` when there is one lane."""
+    small ones.  `tuning` (one engine tuning, or one per lane) can cap the
+    workgroups of the small-query lanes' launches (grid_cap), so that their
+    work fills the device around a large query instead of displacing it.
+    `streams` (optional) gives each lane's stream; by default a new torch
+    stream per lane, or `stream` when there is one lane."""
 
     def __init__(self, graphs: Dict[str, Graph], max_queries=32, hbm_budget_bytes: int = 0,
                  tuning: Optional[dict] = None, stream=None, lanes: Optional[Sequence[int]] = None,
@@ -116,7 +119,10 @@ class Server:
         slots = list(max_queries) if isinstance(max_queries, (list, tuple)) else [max_queries] * nl
         if len(slots) != nl:
             raise ValueError("max_queries needs one value per lane")
-        self.lanes = [_Lane(self, i, slots[i], hbm_budget_bytes, tuning, streams[i]) for i in range(nl)]
+        tunings = list(tuning) if isinstance(tuning, (list, tuple)) else [tuning] * nl
+        if len(tunings) != nl:
+            raise ValueError("tuning needs one value per lane")
+        self.lanes = [_Lane(self, i, slots[i], hbm_budget_bytes, tunings[i], streams[i]) for i in range(nl)]
 
     @property
     def steps(self) -> int:

@@ -254,3 +254,20 @@ def test_engine_graph_mode_two_kernel_choices(imx):
     for qid, r in zip(ids, solo):
         _same(res[qid], r)
     E.free()
+
+
+def test_engine_grid_cap_and_tail_modes(imx):
+    """A workgroup cap on every launch and each tail mode change the schedule,
+    never the results."""
+    cases = _graphs()[:4]
+    Gs = [imx.Graph.from_graphgen(g) for g, *_ in cases]
+    solo = [_solo(imx, G, J, s, K) for G, (_, J, s, K) in zip(Gs, cases)]
+    for tuning in (dict(grid_cap=3), dict(grid_cap=40, tails=1), dict(tails=0), dict(tails=1, use_graphs=1)):
+        E = imx.Engine(max_queries=len(cases))
+        E.set_tuning(**tuning)
+        assert {k: E.get_tuning()[k] for k in tuning} == tuning
+        ids = [E.submit(G, J, s, K) for G, (_, J, s, K) in zip(Gs, cases)]
+        res = E.run()
+        for qid, r in zip(ids, solo):
+            _same(res[qid], r)
+        E.free()
