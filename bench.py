@@ -349,7 +349,9 @@ def served_main(args):
                "serial": {"queries": nq, "throughput_qps": nq / fin, "p50_ms": float(np.percentile(lat, 50)),
                           "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()), "makespan_s": fin}}
         srv = serve.Server(graphs, max_queries=slots, stream=stream, lanes=lanes, tuning=tunings).start()
-        res, span = serve.replay(srv, trace)
+        t_rep = time.perf_counter()
+        res, span = serve.replay(srv, trace, progress=lambda what, i: print(
+            f"[bench] load {load}: {what} {i}/{nq} ({time.perf_counter() - t_rep:.0f} s)", file=sys.stderr, flush=True))
         srv.stop()
         row["continuous_batching"] = serve.latency_summary(res, span)
         for r, ref in zip(res, serial_out):

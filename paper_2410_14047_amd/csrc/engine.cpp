@@ -107,6 +107,7 @@ struct Query {
     uint32_t lv_pending = ~0u;    // level whose flags the next step must compact first (~0u: none)
     bool small_front = false;     // the last sweep (level) seen left a frontier small enough for a tail kernel
     int tail_kind = 0;            // this step: 1 tail sweeps, 2 tail levels, 0 none
+    int nparts = 0;               // partials of the last argmax (the lazy argmax's partition)
     bool tails_ok = false;        // tail kernels may serve this query (engine tail mode and graph degrees)
     int32_t* chg_list2 = nullptr; // second in-task list of the tail sweeps
     int k = 0;
@@ -254,6 +255,7 @@ public:
             A.alloc(&q->is_seed, n) || A.alloc(&q->best, 1) || A.alloc(&q->c.q[0], nt) || A.alloc(&q->c.q[1], nt) ||
             A.alloc(&q->c.lv8, flag_bytes(n)) || A.alloc(&q->c.touched, n) || A.alloc(&q->c.touch_stamp, n) ||
             A.alloc(&q->am.pJ, kArgmaxBlocks) || A.alloc(&q->am.pH, kArgmaxBlocks) || A.alloc(&q->am.pid, kArgmaxBlocks) ||
+            A.alloc(&q->am.dirty, kArgmaxBlocks) ||
             A.alloc(&q->chg_list2, nit) || A.alloc(&q->sw.act_blk, blk_bytes(n)) || A.alloc(&q->c.lv_blk, blk_bytes(n))) {
             A.release();
             return set_error(IM_ENOMEM, "device allocation failed");
@@ -279,6 +281,7 @@ public:
 
         hipError_t e = hipMemsetAsync(S, 0, sizeof(SlotStatus), st_);
         if (e == hipSuccess) e = hipMemsetAsync(q->is_seed, 0, n, st_);
+        if (e == hipSuccess) e = hipMemsetAsync(q->am.dirty, 1, kArgmaxBlocks, st_);
         if (e == hipSuccess) e = hipMemsetAsync(q->sw.act8, 0, flag_bytes(n), st_);
         if (e == hipSuccess) e = hipMemsetAsync(q->c.lv8, 0, flag_bytes(n), st_);
         if (e == hipSuccess) e = hipMemsetAsync(q->sw.act_blk, 0, blk_bytes(n), st_);
@@ -680,7 +683,7 @@ im_status Engine::step()
     for (auto& ch : mchunks(members(est_all))) {
         Launch<EstArgs> L;
         for (auto [q, on] : ch) {
-            L.args.push_back(with(EstArgs{q->M, q->g->n, q->J, q->Ju, q->Hu}, on));
+            L.args.push_back(with(EstArgs{q->M, q->g->n, q->J, q->Ju, q->Hu, q->am.dirty}, on));
             const int64_t rows_per_wg = kWG / row_lanes(q->J) * kRowBatch;
             L.want.push_back(std::min<int64_t>(cus * 16, (q->g->n + rows_per_wg - 1) / rows_per_wg));
         }
@@ -695,8 +698,13 @@ im_status Engine::step()
             // graph mode: few partial workgroups per query (every query's are launched every step)
             const int nparts =
                 (int)std::min<int64_t>(graph_mode ? kGraphArgmaxBlocks : kArgmaxBlocks, (q->g->n + 255) / 256);
-            L.args.push_back(
-                with(ArgmaxArgs{q->Ju, q->Hu, q->is_seed, q->g->n, q->am, q->best, std::max(nparts, 1)}, on));
+            // a change of the partition (graph mode switched) makes every partial stale
+            ArgmaxScratch am = q->am;
+            if (on && std::max(nparts, 1) != q->nparts) {
+                am.dirty = nullptr;
+                q->nparts = std::max(nparts, 1);
+            }
+            L.args.push_back(with(ArgmaxArgs{q->Ju, q->Hu, q->is_seed, q->g->n, am, q->best, std::max(nparts, 1)}, on));
             L.want.push_back(std::max(nparts, 1));
             S.args.push_back(with(SeedArgs{q->g->dev(), q->best, q->k, q->M, q->J, q->is_seed, q->seeds, q->pickJ,
                                            q->pickH, q->Ju, q->Hu, q->c, q->cascade_id},
@@ -738,7 +746,9 @@ im_status Engine::step()
     for (auto& ch : mchunks(members(fin_q))) {
         Launch<FinArgs> L;
         for (auto [q, on] : ch) {
-            L.args.push_back(with(FinArgs{q->M, q->J, q->Ju, q->Hu, q->c}, on));
+            // no partition yet (no pick made): no lazy flags to keep
+            L.args.push_back(
+                with(FinArgs{q->M, q->J, q->Ju, q->Hu, q->c, q->nparts > 0 ? q->am.dirty : nullptr, q->nparts}, on));
             L.want.push_back(std::min<int64_t>(cus * 8, (q->g->n + 4 * kWaves - 1) / (4 * kWaves)));
         }
         L_fin.push_back(std::move(L));
@@ -797,11 +807,24 @@ im_status Engine::step()
     // ---- stage argument records, one copy; the tick's launch structure
     // (kinds, grids, batch splits, record offsets) forms its graph key
     std::vector<int64_t> key;
+    // Graph mode: the grid-stride kinds split their workgroups among the
+    // queries on the device, by each query's current work (inactive queries
+    // get none), so the fixed launch sequence does not starve the active
+    // ones; the argmax (its partial count per query is fixed), the seed step
+    // and the tail kernels (one workgroup per query) keep host splits.
+    auto dynamic_kind = [](int kind) { return kind != 6 && kind != 7 && kind != 12 && kind != 14; };
     auto finish = [&](int kind, auto& L, int64_t cap) -> bool {
         L.dev = stage_args(L.args);
         if (tune_.grid_cap > 0 && kind != 6)  // the partial argmax keeps its per-query partial count
             cap = cap > 0 ? std::min<int64_t>(cap, tune_.grid_cap) : tune_.grid_cap;
-        L.B = make_batch(L.want, cap);
+        if (graph_mode && dynamic_kind(kind)) {
+            L.B = Batch{};
+            L.B.nq = (int)L.args.size();
+            L.B.wg0[0] = -1;
+            L.B.wg0[L.B.nq] = (int)std::max<int64_t>(cap > 0 ? cap : (int64_t)cus * 8, L.B.nq);
+        } else {
+            L.B = make_batch(L.want, cap);
+        }
         key.push_back(kind);
         key.push_back(L.dev ? reinterpret_cast<const uint8_t*>(L.dev) - args_dev_ : -1);
         key.push_back(L.maxJ);

@@ -158,6 +158,11 @@ struct ArgmaxScratchT {
     dptr<uint32_t, G> pJ;            // [kArgmaxBlocks]
     dptr<unsigned long long, G> pH;  // [kArgmaxBlocks]
     dptr<int32_t, G> pid;            // [kArgmaxBlocks]
+    // Lazy selection: partial b is recomputed only when dirty[b] != 0, i.e.
+    // when a vertex of its block changed its estimate terms or seed flag since
+    // the partial was last computed (the cascade's finalize and the estimate
+    // pass set the flags).  nullptr: every partial is recomputed.
+    dptr<uint8_t, G> dirty = nullptr;  // [kArgmaxBlocks]
 };
 using ArgmaxScratch = ArgmaxScratchT<false>;
 
@@ -235,6 +240,7 @@ struct EstArgsT {
     int J;
     dptr<uint32_t, G> Ju;
     dptr<unsigned long long, G> Hu;
+    dptr<uint8_t, G> am_dirty = nullptr;  // every partial of the lazy argmax becomes dirty (or nullptr)
     int active = 1;  // 0: this query skips the launch (fixed launch sequences of the engine's graph mode)
 };
 using EstArgs = EstArgsT<false>;
@@ -301,6 +307,8 @@ struct FinArgsT {
     dptr<uint32_t, G> Ju;
     dptr<unsigned long long, G> Hu;
     CascadeDevT<G> c;
+    dptr<uint8_t, G> am_dirty = nullptr;  // the lazy argmax's partial of every touched row becomes dirty (or nullptr)
+    int nparts = 1;                       // partials of the query's argmax
     int active = 1;  // 0: this query skips the launch (fixed launch sequences of the engine's graph mode)
 };
 using FinArgs = FinArgsT<false>;

@@ -424,11 +424,86 @@ __device__ __forceinline__ const S<true>& gview(const S<false>& x)
     return reinterpret_cast<const S<true>&>(x);
 }
 
+// Work of a record now (read from the device counters the earlier kernels of
+// the step left), for the dynamic split below.
+template <class R>
+__device__ __forceinline__ unsigned long long work_weight(const R&) { return 1ull; }
+__device__ __forceinline__ unsigned long long work_weight(const PropArgsT<true>& a)
+{
+    return (a.tasks == nullptr || *a.dense != 0u) ? (unsigned long long)a.g.ntasks : (unsigned long long)*a.task_count;
+}
+__device__ __forceinline__ unsigned long long work_weight(const LevelArgsT<true>& a)
+{
+    return a.c.qsize[a.t & 3];
+}
+__device__ __forceinline__ unsigned long long work_weight(const MarkArgsT<true>& a)
+{
+    return a.s.chg_count[a.sweep & 3];
+}
+__device__ __forceinline__ unsigned long long work_weight(const FillArgsT<true>& a) { return (unsigned long long)a.n; }
+__device__ __forceinline__ unsigned long long work_weight(const EstArgsT<true>& a) { return (unsigned long long)a.n; }
+__device__ __forceinline__ unsigned long long work_weight(const PrepArgsT<true>& a)
+{
+    return (unsigned long long)a.n >> 10;
+}
+__device__ __forceinline__ unsigned long long work_weight(const LevelCompactArgsT<true>& a)
+{
+    return (unsigned long long)a.n >> 10;
+}
+__device__ __forceinline__ unsigned long long work_weight(const FinArgsT<true>& a)
+{
+    return (*a.c.level_end != ~0u) ? (unsigned long long)*a.c.ntouched : 0ull;
+}
+
+// Dynamic split (B.wg0[0] == -1, B.wg0[B.nq] = the grid): the launch's
+// workgroups are divided among the records at run time, each active record
+// getting one plus a share of the rest in proportion to its current work, so
+// a launch whose sequence is fixed (graph mode) spends no workgroups on
+// queries without work in it.  Lane i of every wave computes record i's share
+// (kMaxBatch = 64 records at most); every wave reaches the same split.  The
+// host makes the grid at least the number of records.  Returns false for a
+// workgroup left without a record.
+template <class A>
+__device__ __forceinline__ bool dyn_split(const A* args, const Batch& B, int& bi, int64_t& lb, int64_t& lg)
+{
+    static_assert(kMaxBatch <= 64, "one lane per record");
+    const int lane = lane_id();
+    unsigned long long w = 0ull;
+    if (lane < B.nq) {
+        const auto& r = gview(args[lane]);
+        if (r.active) {
+            const unsigned long long ww = work_weight(r);
+            w = ww > 0ull ? ww : 1ull;
+        }
+    }
+    const unsigned long long W = wave_sum_u64(w);
+    const int nact = __popcll(__ballot(w > 0ull));
+    const int64_t G = gridDim.x;
+    const int64_t rest = G > nact ? G - nact : 0;
+    const int blocks = (w > 0ull) ? 1 + (int)((unsigned long long)rest * w / (W > 0ull ? W : 1ull)) : 0;
+    const int incl = wave_incl_scan(blocks);
+    const int64_t start = incl - blocks;
+    const int64_t b = blockIdx.x;
+    const unsigned long long mine = __ballot(blocks > 0 && b >= start && b < (int64_t)incl);
+    if (mine == 0ull) return false;
+    const int l = __ffsll((long long)mine) - 1;
+    bi = l;
+    lb = b - lane_val((int)start, l);
+    lg = lane_val(blocks, l);
+    return true;
+}
+
 #define IMX_BATCH_PROLOGUE(ArgsT)                                     \
-    const int bi_ = batch_index(B);                                   \
+    int bi_ = 0;                                                      \
+    int64_t lb = 0, lg = 1;                                           \
+    if (B.wg0[0] < 0) {                                               \
+        if (!dyn_split(args, B, bi_, lb, lg)) return;                 \
+    } else {                                                          \
+        bi_ = batch_index(B);                                         \
+        lb = (int64_t)blockIdx.x - B.wg0[bi_];                        \
+        lg = (int64_t)B.wg0[bi_ + 1] - B.wg0[bi_];                    \
+    }                                                                 \
     const auto& a = gview(args[bi_]);                                 \
-    const int64_t lb = (int64_t)blockIdx.x - B.wg0[bi_];              \
-    const int64_t lg = (int64_t)B.wg0[bi_ + 1] - B.wg0[bi_];          \
     (void)lb;                                                         \
     (void)lg;                                                         \
     if (!a.active) return
@@ -1636,6 +1711,8 @@ __device__ __forceinline__ void est_word(uint32_t d, uint32_t& c, unsigned long 
 __global__ __launch_bounds__(kWG) void k_estimate(const EstArgs* __restrict__ args, Batch B)
 {
     IMX_BATCH_PROLOGUE(EstArgs);
+    if (a.am_dirty != nullptr && lb == 0)  // every estimate term is recomputed
+        for (int i = threadIdx.x; i < kArgmaxBlocks; i += blockDim.x) a.am_dirty[i] = 1u;
     const int L = row_lanes(a.J);
     const int lane = lane_id();
     const int sub = lane % L;
@@ -1747,6 +1824,7 @@ __global__ __launch_bounds__(256) void k_argmax_partial(const ArgmaxArgs* __rest
 {
     IMX_BATCH_PROLOGUE(ArgmaxArgs);
     for (int64_t b = lb; b < a.nparts; b += lg) {
+        if (a.am.dirty != nullptr && a.am.dirty[b] == 0u) continue;  // unchanged since computed (uniform)
         Cand best{0u, 0ull, -1};
         for (int64_t v = b * blockDim.x + threadIdx.x; v < a.n; v += (int64_t)a.nparts * blockDim.x) {
             if (a.is_seed[v]) continue;
@@ -1758,6 +1836,7 @@ __global__ __launch_bounds__(256) void k_argmax_partial(const ArgmaxArgs* __rest
             a.am.pJ[b] = best.J;
             a.am.pH[b] = best.H;
             a.am.pid[b] = best.id;
+            if (a.am.dirty != nullptr) a.am.dirty[b] = 0u;
         }
         __syncthreads();  // block_reduce_best's LDS is reused by the next partial
     }
@@ -2217,6 +2296,8 @@ __global__ __launch_bounds__(kWG) void k_cascade_finalize(const FinArgs* __restr
                 a.Ju[vv[r]] = cs;
                 a.Hu[vv[r]] = hs;
                 dT += (unsigned long long)(old - cs);
+                if (a.am_dirty != nullptr && a.nparts > 0)
+                    a.am_dirty[((uint32_t)vv[r] >> 8) % (uint32_t)a.nparts] = 1u;
             }
         }
     }

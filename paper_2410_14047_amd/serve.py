@@ -185,17 +185,24 @@ class Server:
                 req["future"].set_exception(e)
 
 
-def replay(server: Server, trace, time_scale: float = 1.0):
+def replay(server: Server, trace, time_scale: float = 1.0, progress=None, every: int = 50):
     """Submit a trace of (t_arrival_s, graph, J, seed, K) at its arrival times;
-    return (results in trace order, makespan seconds)."""
+    return (results in trace order, makespan seconds).  `progress(i, n)` (if
+    given) is called after every `every` submissions and completions."""
     t0 = time.perf_counter()
     futs = []
-    for (ta, graph, J, seed, K) in trace:
+    for i, (ta, graph, J, seed, K) in enumerate(trace):
         delay = t0 + ta * time_scale - time.perf_counter()
         if delay > 0:
             time.sleep(delay)
         futs.append(server.submit(graph, J, seed, K))
-    res = [f.result() for f in futs]
+        if progress and (i + 1) % every == 0:
+            progress("submitted", i + 1)
+    res = []
+    for i, f in enumerate(futs):
+        res.append(f.result())
+        if progress and (i + 1) % every == 0:
+            progress("completed", i + 1)
     return res, time.perf_counter() - t0
 
 
