@@ -333,8 +333,29 @@ def served_main(args):
            "unit": "queries/s", "n_gpus": 1, "mean_serial_service_s": svc, "levels": []}
     slots = [int(x) for x in args.served_slots.split(",")]
     lanes = [int(x) << 20 for x in args.served_lanes_mib.split(",")]
+    # lanes whose streams are restricted to a subset of the compute units
+    # (hipExtStreamCreateWithCUMask; 0x55555555 = every other CU)
+    streams = None
+    if args.served_cu_masks:
+        import ctypes
+        hip = ctypes.CDLL("libamdhip64.so")
+        hip.hipExtStreamCreateWithCUMask.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint32,
+                                                     ctypes.POINTER(ctypes.c_uint32)]
+        masks = [int(x, 16) for x in args.served_cu_masks.split(",")]
+        streams = []
+        for mk in masks:
+            if mk == 0:
+                streams.append(torch.cuda.Stream())
+                continue
+            words = (ctypes.c_uint32 * 8)(*([mk] * 8))
+            h = ctypes.c_void_p()
+            rc = hip.hipExtStreamCreateWithCUMask(ctypes.byref(h), 8, words)
+            if rc != 0:
+                raise SystemExit(f"hipExtStreamCreateWithCUMask failed: {rc}")
+            streams.append(h.value)
     caps = [int(x) for x in args.served_caps.split(",")]
-    tunings = [dict(grid_cap=c) for c in caps]
+    graphs_on = [int(x) for x in args.served_graphs.split(",")]
+    tunings = [dict(grid_cap=c, use_graphs=u) for c, u in zip(caps, graphs_on)]
     for load in [float(x) for x in args.served_loads.split(",")]:
         lam = load / svc
         arr = np.cumsum(np.random.Generator(np.random.PCG64(int(round(load * 1000)))).exponential(1.0 / lam, size=nq))
@@ -348,7 +369,8 @@ def served_main(args):
         row = {"load": load, "lambda_qps": lam,
                "serial": {"queries": nq, "throughput_qps": nq / fin, "p50_ms": float(np.percentile(lat, 50)),
                           "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()), "makespan_s": fin}}
-        srv = serve.Server(graphs, max_queries=slots, stream=stream, lanes=lanes, tuning=tunings).start()
+        srv = serve.Server(graphs, max_queries=slots, stream=stream, lanes=lanes, tuning=tunings,
+                           streams=streams).start()
         t_rep = time.perf_counter()
         res, span = serve.replay(srv, trace, progress=lambda what, i: print(
             f"[bench] load {load}: {what} {i}/{nq} ({time.perf_counter() - t_rep:.0f} s)", file=sys.stderr, flush=True))
@@ -364,7 +386,8 @@ def served_main(args):
     out["value"] = max(r["continuous_batching"]["throughput_qps"] for r in out["levels"])
     out["config"] = {"workload": "served_rmat" + "-".join(map(str, scales)) + "_p0.01+wc_J128|512_K10-100",
                      "queries_per_level": nq, "slots_per_lane": args.served_slots,
-                     "lanes_mib": args.served_lanes_mib, "lane_grid_caps": args.served_caps}
+                     "lanes_mib": args.served_lanes_mib, "lane_grid_caps": args.served_caps,
+                     "lane_graph_mode": args.served_graphs}
     print(json.dumps(out), flush=True)
 
 
@@ -454,6 +477,10 @@ def main():
     ap.add_argument("--served-slots", default="16,8,1", help="queries each lane holds at once")
     ap.add_argument("--served-caps", default="0,0,0",
                     help="workgroup cap of every launch of each lane's engine (0: none)")
+    ap.add_argument("--served-cu-masks", default="",
+                    help="hex CU mask (every 32-CU word) of each lane's stream, 0 for an unrestricted stream")
+    ap.add_argument("--served-graphs", default="0,0,0",
+                    help="graph mode (captured steps, device-side splits) of each lane's engine")
     ap.add_argument("--served-service-out", default="", help="write the serial pass (service times, outputs) here")
     ap.add_argument("--served-service-in", default="", help="reuse a serial pass written by --served-service-out")
     ap.add_argument("--served-lanes-mib", default="128,1024",

@@ -187,6 +187,9 @@ public:
         if (const char* v = std::getenv("IMX_TAIL_ROWS")) tail_rows_ = std::max(0, std::atoi(v));
         if (const char* v = std::getenv("IMX_TAIL_TASKS")) tail_tasks_ = std::max(1, std::atoi(v));
         if (const char* v = std::getenv("IMX_TAIL_ROUNDS")) tail_rounds_ = std::max(1, std::atoi(v));
+        // Device-side workgroup splits for direct launches of several queries
+        // (graph mode always uses them); IMX_DYN_SPLIT=0 keeps host splits.
+        if (const char* v = std::getenv("IMX_DYN_SPLIT")) dyn_split_ = std::atoi(v) != 0;
         if (const char* v = std::getenv("IMX_PROP_GRID")) {
             prop_grid_cap_ = std::atoi(v);
             if (prop_grid_cap_ < 1) return set_error(IM_EINVAL, "IMX_PROP_GRID must be >= 1");
@@ -475,6 +478,7 @@ private:
     int cap_;
     size_t budget_;
     int64_t prop_grid_cap_ = 0;  // IMX_PROP_GRID (0: none)
+    bool dyn_split_ = true;      // IMX_DYN_SPLIT
     // Tail kernels: a query whose last sweep changed at most tail_rows_ rows
     // (or whose next level has at most tail_tasks_ tasks, or a new cascade)
     // runs up to tail_rounds_ sweeps (levels) in one single-workgroup launch;
@@ -807,17 +811,19 @@ im_status Engine::step()
     // ---- stage argument records, one copy; the tick's launch structure
     // (kinds, grids, batch splits, record offsets) forms its graph key
     std::vector<int64_t> key;
-    // Graph mode: the grid-stride kinds split their workgroups among the
-    // queries on the device, by each query's current work (inactive queries
-    // get none), so the fixed launch sequence does not starve the active
-    // ones; the argmax (its partial count per query is fixed), the seed step
-    // and the tail kernels (one workgroup per query) keep host splits.
+    // Launches of several queries (and every launch in graph mode) split
+    // their workgroups among the queries on the device, by each query's
+    // current work (inactive queries get none): the host's split by graph
+    // size ignores how much of a graph a sweep or level touches, and in graph
+    // mode the fixed launch sequence would starve the active queries.  The
+    // argmax (its partial count per query is fixed), the seed step and the
+    // tail kernels (one workgroup per query) keep host splits.
     auto dynamic_kind = [](int kind) { return kind != 6 && kind != 7 && kind != 12 && kind != 14; };
     auto finish = [&](int kind, auto& L, int64_t cap) -> bool {
         L.dev = stage_args(L.args);
         if (tune_.grid_cap > 0 && kind != 6)  // the partial argmax keeps its per-query partial count
             cap = cap > 0 ? std::min<int64_t>(cap, tune_.grid_cap) : tune_.grid_cap;
-        if (graph_mode && dynamic_kind(kind)) {
+        if ((graph_mode || (dyn_split_ && L.args.size() > 1)) && dynamic_kind(kind)) {
             L.B = Batch{};
             L.B.nq = (int)L.args.size();
             L.B.wg0[0] = -1;
@@ -1334,6 +1340,14 @@ im_status im_select_seeds_batch(int32_t G, const im_graph* const* graphs, const 
     if (G < 1 || !graphs || !J || !seed || !K || !seeds_out) return imx::set_error(IM_EINVAL, "NULL argument");
     im_engine* e = nullptr;
     if (im_status st = im_engine_create(G, 0, stream, &e)) return st;
+    // many queries of one call: captured steps with device-side splits (the
+    // launch sequence changes only when a query finishes)
+    im_tuning t = e->eng->tuning();
+    t.use_graphs = 1;
+    if (im_status st = e->eng->set_tuning(t)) {
+        im_engine_free(e);
+        return st;
+    }
     std::vector<int64_t> ids(G);
     for (int32_t i = 0; i < G; ++i)
         if (im_status st = im_engine_submit(e, graphs[i], J[i], seed[i], K[i], &ids[i])) {
