@@ -122,6 +122,32 @@ def pmc_summary(args):
     print(json.dumps(d))
 
 
+def liveness_stats():
+    """How an arc's live simulations spread over the J = 1024 sorted
+    simulation values, which decides what sample-space tiling could save on
+    one GPU: live simulations per arc, arcs dead in all of them, 128-simulation
+    tiles with a live one, and 64-byte register sectors the candidate range
+    touches.  Uniform 31-bit arc hashes and uniform simulation values (the
+    distribution the hash and the simulation-value generator are built to
+    give); CPU only."""
+    import numpy as np
+    rng = np.random.default_rng(7)
+    J, T = 1024, 128
+    X = np.sort(rng.integers(0, 2**31, J, dtype=np.int64))
+    for p in (0.001, 0.005, 0.01, 0.1):
+        W = int(np.floor(np.float32(p) * 2**31))
+        h = rng.integers(0, 2**31, 200_000, dtype=np.int64)
+        live = (X[None, :] ^ h[:, None]) < W  # arcs x simulations
+        nlive = live.sum(1)
+        tiles = live.reshape(len(h), J // T, T).any(2).sum(1)
+        first = np.where(nlive > 0, live.argmax(1), 0)
+        last = np.where(nlive > 0, J - 1 - live[:, ::-1].argmax(1), -1)
+        sectors = np.where(nlive > 0, last // 64 - first // 64 + 1, 0)
+        print(json.dumps({"p": p, "live_sims_per_arc": float(nlive.mean()), "dead_arcs": float(np.mean(nlive == 0)),
+                          f"live_{T}_sim_tiles_per_arc": float(tiles.mean()),
+                          "sectors_per_arc": float(sectors.mean())}), flush=True)
+
+
 def gather_calibration(mib: int):
     """Access-rate ceilings of the device memory (libimx_probe.so): random
     gathers of 16 B (from 64-byte-aligned positions), 64, 128, 256 and 1024 B,
@@ -333,26 +359,6 @@ def served_main(args):
            "unit": "queries/s", "n_gpus": 1, "mean_serial_service_s": svc, "levels": []}
     slots = [int(x) for x in args.served_slots.split(",")]
     lanes = [int(x) << 20 for x in args.served_lanes_mib.split(",")]
-    # lanes whose streams are restricted to a subset of the compute units
-    # (hipExtStreamCreateWithCUMask; 0x55555555 = every other CU)
-    streams = None
-    if args.served_cu_masks:
-        import ctypes
-        hip = ctypes.CDLL("libamdhip64.so")
-        hip.hipExtStreamCreateWithCUMask.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint32,
-                                                     ctypes.POINTER(ctypes.c_uint32)]
-        masks = [int(x, 16) for x in args.served_cu_masks.split(",")]
-        streams = []
-        for mk in masks:
-            if mk == 0:
-                streams.append(torch.cuda.Stream())
-                continue
-            words = (ctypes.c_uint32 * 8)(*([mk] * 8))
-            h = ctypes.c_void_p()
-            rc = hip.hipExtStreamCreateWithCUMask(ctypes.byref(h), 8, words)
-            if rc != 0:
-                raise SystemExit(f"hipExtStreamCreateWithCUMask failed: {rc}")
-            streams.append(h.value)
     caps = [int(x) for x in args.served_caps.split(",")]
     graphs_on = [int(x) for x in args.served_graphs.split(",")]
     tunings = [dict(grid_cap=c, use_graphs=u) for c, u in zip(caps, graphs_on)]
@@ -370,7 +376,7 @@ def served_main(args):
                "serial": {"queries": nq, "throughput_qps": nq / fin, "p50_ms": float(np.percentile(lat, 50)),
                           "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()), "makespan_s": fin}}
         srv = serve.Server(graphs, max_queries=slots, stream=stream, lanes=lanes, tuning=tunings,
-                           streams=streams).start()
+                           quick_s=args.served_quick_ms * 1e-3).start()
         t_rep = time.perf_counter()
         res, span = serve.replay(srv, trace, progress=lambda what, i: print(
             f"[bench] load {load}: {what} {i}/{nq} ({time.perf_counter() - t_rep:.0f} s)", file=sys.stderr, flush=True))
@@ -380,6 +386,10 @@ def served_main(args):
             assert [int(x) for x in r["seeds"]] == ref["seeds"] and [int(x) for x in r["T"]] == ref["T"], \
                 "outputs differ"
         row["identical_outputs"] = True
+        if args.served_dump:
+            dump = json.load(open(args.served_dump)) if os.path.exists(args.served_dump) else {}
+            dump[str(load)] = {"serial_ms": lat.tolist(), "cb_ms": [r["latency_s"] * 1e3 for r in res]}
+            json.dump(dump, open(args.served_dump, "w"))
         print(f"[bench] load {load}: serial {row['serial']} | continuous batching {row['continuous_batching']}",
               file=sys.stderr, flush=True)
         out["levels"].append(row)
@@ -387,7 +397,7 @@ def served_main(args):
     out["config"] = {"workload": "served_rmat" + "-".join(map(str, scales)) + "_p0.01+wc_J128|512_K10-100",
                      "queries_per_level": nq, "slots_per_lane": args.served_slots,
                      "lanes_mib": args.served_lanes_mib, "lane_grid_caps": args.served_caps,
-                     "lane_graph_mode": args.served_graphs}
+                     "lane_graph_mode": args.served_graphs, "quick_ms": args.served_quick_ms}
     print(json.dumps(out), flush=True)
 
 
@@ -477,14 +487,17 @@ def main():
     ap.add_argument("--served-slots", default="16,8,1", help="queries each lane holds at once")
     ap.add_argument("--served-caps", default="0,0,0",
                     help="workgroup cap of every launch of each lane's engine (0: none)")
-    ap.add_argument("--served-cu-masks", default="",
-                    help="hex CU mask (every 32-CU word) of each lane's stream, 0 for an unrestricted stream")
+    ap.add_argument("--served-quick-ms", type=float, default=0.0,
+                    help="route (graph, J) classes seen to finish within this many ms to the first lane (0: off)")
+    ap.add_argument("--served-dump", default="", help="write every query's latency (serial and batched) here")
     ap.add_argument("--served-graphs", default="0,0,0",
                     help="graph mode (captured steps, device-side splits) of each lane's engine")
     ap.add_argument("--served-service-out", default="", help="write the serial pass (service times, outputs) here")
     ap.add_argument("--served-service-in", default="", help="reuse a serial pass written by --served-service-out")
     ap.add_argument("--served-lanes-mib", default="128,1024",
                     help="footprint bounds (MiB) of the serving lanes; larger queries take the last lane")
+    ap.add_argument("--liveness-stats", action="store_true",
+                    help="print how arcs' live simulations spread over the sorted values (CPU only)")
     ap.add_argument("--gather-calibration", type=int, default=0, metavar="MIB",
                     help="only measure random gathers of 64/128/1024-byte rows from a MIB MiB buffer "
                          "and a streaming copy (the access-rate ceilings of the propagation kernel)")
@@ -507,6 +520,8 @@ def main():
         return served_main(args)
     if args.workload == "quality":
         return quality_main(args)
+    if args.liveness_stats:
+        return liveness_stats()
     if args.gather_calibration:
         return gather_calibration(args.gather_calibration)
     if args.copy_calibration:

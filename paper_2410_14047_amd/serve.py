@@ -12,7 +12,13 @@ Queries are routed to lanes by device footprint (n * J plus work arrays):
 small queries finish in a few hundred launches, large ones in a few
 thousand, and a step lasts as long as its largest query, so keeping them on
 separate engines (whose streams run concurrently on the GPU) stops small
-queries from waiting in lock step behind large ones.  Latency is measured
+queries from waiting in lock step behind large ones.  Footprint is not
+work, though: on a subcritical probability setting a query on a large graph
+converges in a few sweeps and short cascades.  With `quick_s` set, the server
+learns, per (graph, J), the shortest time a query of that class has spent in
+an engine (admission to completion), and sends a class seen to finish within
+`quick_s` to the first lane whatever its footprint, so such queries do not
+queue behind the long ones of their footprint's lane.  Latency is measured
 from submit() to completion.  Results do not depend on the lane or the mix.
 """
 from __future__ import annotations
@@ -78,6 +84,7 @@ class _Lane:
                         req = self.live.pop(qid)
                         res = self.engine.result(qid)
                         req["t_done"] = time.perf_counter()
+                        srv._observe(req["graph"], req["J"], req["t_done"] - req["t_admit"])
                         res["latency_s"] = req["t_done"] - req["t_arrival"]
                         res["queue_s"] = req["t_admit"] - req["t_arrival"]
                         res["lane"] = self.index
@@ -98,12 +105,16 @@ class Server:
     workgroups of the small-query lanes' launches (grid_cap), so that their
     work fills the device around a large query instead of displacing it.
     `streams` (optional) gives each lane's stream; by default a new torch
-    stream per lane, or `stream` when there is one lane."""
+    stream per lane, or `stream` when there is one lane.  `quick_s` (seconds,
+    0: off) routes classes (graph, J) seen to finish within it in an engine to
+    the first lane."""
 
     def __init__(self, graphs: Dict[str, Graph], max_queries=32, hbm_budget_bytes: int = 0,
                  tuning: Optional[dict] = None, stream=None, lanes: Optional[Sequence[int]] = None,
-                 streams: Optional[Sequence] = None):
+                 streams: Optional[Sequence] = None, quick_s: float = 0.0):
         self.graphs = dict(graphs)
+        self.quick_s = float(quick_s)
+        self._shortest: Dict[tuple, float] = {}  # (graph, J) -> shortest admission-to-completion time
         self.bounds: List[int] = list(lanes) if lanes else []
         nl = len(self.bounds) + 1
         if streams is None:
@@ -128,8 +139,15 @@ class Server:
     def steps(self) -> int:
         return sum(l.steps for l in self.lanes)
 
+    def _observe(self, graph: str, J: int, seconds: float) -> None:
+        with self._cv:
+            key = (graph, J)
+            self._shortest[key] = min(seconds, self._shortest.get(key, float("inf")))
+
     def _route(self, graph: str, J: int, K: int) -> _Lane:
         if len(self.lanes) == 1:
+            return self.lanes[0]
+        if self.quick_s > 0 and self._shortest.get((graph, J), float("inf")) <= self.quick_s:
             return self.lanes[0]
         need = im_query_footprint(self.graphs[graph].handle, J, K)
         for lane, bound in zip(self.lanes, self.bounds):

@@ -189,3 +189,33 @@ def test_server_routes_by_footprint(fake, monkeypatch):
     small, large = made
     assert small.admit_order == [0, 2, 4] and large.admit_order == [1, 3]
     assert small.freed and large.freed
+
+
+def test_server_routes_quick_classes_to_first_lane(fake, monkeypatch):
+    """A class (graph, J) seen to finish within quick_s goes to the first lane
+    whatever its footprint; classes not seen yet, or slower, keep the
+    footprint's lane."""
+    fake(slots=2)
+    monkeypatch.setattr(serve, "im_query_footprint", lambda h, J, K: J * 1000)
+    srv = serve.Server({"a": _G("A"), "b": _G("B")}, max_queries=2, lanes=[200_000], streams=[None, None],
+                       quick_s=60.0).start()
+    first = srv.submit("a", 512, 1, 2).result(timeout=10)
+    assert first["lane"] == 1                      # not seen yet: by footprint
+    again = srv.submit("a", 512, 2, 2).result(timeout=10)
+    other_j = srv.submit("a", 1024, 3, 2).result(timeout=10)
+    other_g = srv.submit("b", 512, 4, 2).result(timeout=10)
+    srv.stop()
+    assert again["lane"] == 0                      # seen to finish within quick_s
+    assert other_j["lane"] == 1 and other_g["lane"] == 1
+    assert list(again["seeds"]) == [2, 3]          # results do not depend on the lane
+
+    srv = serve.Server({"a": _G("A")}, max_queries=2, lanes=[200_000], streams=[None, None], quick_s=0.0).start()
+    srv._observe("a", 512, 0.001)
+    assert srv._route("a", 512, 2) is srv.lanes[1]  # quick_s = 0: footprint only
+    srv.stop()
+    srv = serve.Server({"a": _G("A")}, max_queries=2, lanes=[200_000], streams=[None, None], quick_s=0.05).start()
+    srv._observe("a", 512, 0.2)
+    assert srv._route("a", 512, 2) is srv.lanes[1]  # slower than quick_s
+    srv._observe("a", 512, 0.04)
+    assert srv._route("a", 512, 2) is srv.lanes[0]  # the shortest time counts
+    srv.stop()
