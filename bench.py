@@ -357,11 +357,20 @@ def served_main(args):
     # the trace of each load level: arrivals from their own seeded stream
     out = {"metric": "served IM queries: throughput and p50/p99 latency",
            "unit": "queries/s", "n_gpus": 1, "mean_serial_service_s": svc, "levels": []}
-    slots = [int(x) for x in args.served_slots.split(",")]
     lanes = [int(x) << 20 for x in args.served_lanes_mib.split(",")]
-    caps = [int(x) for x in args.served_caps.split(",")]
-    graphs_on = [int(x) for x in args.served_graphs.split(",")]
-    tunings = [dict(grid_cap=c, use_graphs=u) for c, u in zip(caps, graphs_on)]
+    nl = len(lanes) + 1
+
+    def per_lane(text, what):  # one value for every lane, or one per lane
+        v = [int(x) for x in text.split(",")]
+        if len(v) == 1:
+            v = v * nl
+        if len(v) != nl:
+            raise SystemExit(f"--served-{what} needs 1 or {nl} values")
+        return v
+
+    slots = per_lane(args.served_slots, "slots")
+    tunings = [dict(grid_cap=c, use_graphs=u) for c, u in
+               zip(per_lane(args.served_caps, "caps"), per_lane(args.served_graphs, "graphs"))]
     for load in [float(x) for x in args.served_loads.split(",")]:
         lam = load / svc
         arr = np.cumsum(np.random.Generator(np.random.PCG64(int(round(load * 1000)))).exponential(1.0 / lam, size=nq))
@@ -425,18 +434,25 @@ def quality_main(args):
     """Seed quality under the paper's weight settings (constant 0.005, 0.01,
     0.1; N(0.05, 0.025); U(0, 0.1)) on an RMAT graph: the GPU's seeds and
     sketch estimate T/J, against the spread of the same seeds by independent
-    Monte-Carlo (3 runs of `--quality-worlds` worlds, standard RNG)."""
+    Monte-Carlo (3 runs of `--quality-worlds` worlds, standard RNG).  The 15
+    Monte-Carlo runs go to a pool of worker processes forked before anything
+    touches the GPU."""
+    import multiprocessing
+
     import numpy as np
 
     import graphgen
+    settings = ("0.005", "0.01", "0.1", "normal", "uniform01")
+    pool = multiprocessing.get_context("fork").Pool(min(3 * len(settings), max(1, os.cpu_count() or 1)))
+
     import torch
 
     import paper_2410_14047_amd as imx
     torch.cuda.set_device(0)
     base = graphgen.rmat(args.quality_scale, 16, seed=1)
     J, K = 1024, 50
-    rows = []
-    for scheme in ("0.005", "0.01", "0.1", "normal", "uniform01"):
+    rows, jobs = [], []
+    for scheme in settings:
         g = graphgen.with_p(base, scheme)
         G = imx.Graph.from_graphgen(g)
         t = time.perf_counter()
@@ -446,12 +462,17 @@ def quality_main(args):
         torch.cuda.synchronize()
         gpu_ms = (time.perf_counter() - t) * 1e3
         G.free()
-        runs = [float(mc_spread(g, r["seeds"], args.quality_worlds, np.random.default_rng(100 + i)).mean())
-                for i in range(3)]
+        jobs += [pool.apply_async(mc_spread, (g, [int(x) for x in r["seeds"]], args.quality_worlds,
+                                              np.random.default_rng(100 + i))) for i in range(3)]
+        rows.append({"setting": scheme, "sketch_spread": float(r["spread"]), "gpu_ms": gpu_ms})
+    for i, row in enumerate(rows):
+        runs = [float(jobs[3 * i + k].get().mean()) for k in range(3)]
         mc = float(np.mean(runs))
-        rows.append({"setting": scheme, "sketch_spread": float(r["spread"]), "mc_spread": mc,
-                     "mc_run_spreads": runs, "sketch_over_mc": float(r["spread"]) / mc, "gpu_ms": gpu_ms})
-        print(f"[bench] quality {scheme}: sketch {r['spread']:.1f} MC {mc:.1f}", file=sys.stderr, flush=True)
+        row.update({"mc_spread": mc, "mc_run_spreads": runs, "sketch_over_mc": row["sketch_spread"] / mc})
+        print(f"[bench] quality {row['setting']}: sketch {row['sketch_spread']:.1f} MC {mc:.1f}", file=sys.stderr,
+              flush=True)
+    pool.close()
+    pool.join()
     out = {"metric": "seed quality: sketch estimate vs independent Monte-Carlo spread of the same seeds",
            "unit": "vertices", "n_gpus": 1, "data": "synthetic", "dtype": "u8",
            "config": {"workload": f"quality_rmat{args.quality_scale}_J{J}_K{K}", "n": base.n, "m": base.m,
@@ -467,7 +488,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + ["batched64", "served", "quality"])
     ap.add_argument("--quality-scale", type=int, default=16, help="RMAT scale of the quality workload")
-    ap.add_argument("--quality-worlds", type=int, default=200, help="Monte-Carlo worlds per run (quality)")
+    ap.add_argument("--quality-worlds", type=int, default=1000, help="Monte-Carlo worlds per run (quality)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-roofline", action="store_true", help="skip the instrumented byte-count pass")
     ap.add_argument("--no-tail", action="store_true",
@@ -484,17 +505,17 @@ def main():
     ap.add_argument("--served-scales", default="16,17,18,19,20,21,22,22")
     ap.add_argument("--served-queries", type=int, default=64)
     ap.add_argument("--served-loads", default="0.5,0.8,1.0")
-    ap.add_argument("--served-slots", default="16,8,1", help="queries each lane holds at once")
-    ap.add_argument("--served-caps", default="0,0,0",
+    ap.add_argument("--served-slots", default="16,1", help="queries each lane holds at once")
+    ap.add_argument("--served-caps", default="0",
                     help="workgroup cap of every launch of each lane's engine (0: none)")
-    ap.add_argument("--served-quick-ms", type=float, default=0.0,
+    ap.add_argument("--served-quick-ms", type=float, default=100.0,
                     help="route (graph, J) classes seen to finish within this many ms to the first lane (0: off)")
     ap.add_argument("--served-dump", default="", help="write every query's latency (serial and batched) here")
-    ap.add_argument("--served-graphs", default="0,0,0",
+    ap.add_argument("--served-graphs", default="0",
                     help="graph mode (captured steps, device-side splits) of each lane's engine")
     ap.add_argument("--served-service-out", default="", help="write the serial pass (service times, outputs) here")
     ap.add_argument("--served-service-in", default="", help="reuse a serial pass written by --served-service-out")
-    ap.add_argument("--served-lanes-mib", default="128,1024",
+    ap.add_argument("--served-lanes-mib", default="128",
                     help="footprint bounds (MiB) of the serving lanes; larger queries take the last lane")
     ap.add_argument("--liveness-stats", action="store_true",
                     help="print how arcs' live simulations spread over the sorted values (CPU only)")
