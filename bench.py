@@ -175,15 +175,24 @@ def gather_calibration(mib: int):
 
 
 def cpu_info():
-    model = ""
+    """Host CPU as /proc/cpuinfo names it: model name, with the family, model
+    and stepping numbers and the clock (a virtual machine may report only a
+    generic model name)."""
+    f = {}
     try:
         for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                model = line.split(":", 1)[1].strip()
+            if ":" in line:
+                k, v = (x.strip() for x in line.split(":", 1))
+                if k in ("model name", "cpu family", "model", "stepping", "cpu MHz") and k not in f:
+                    f[k] = v
+            elif f:
                 break
     except OSError:
         pass
-    return model
+    if not f:
+        return ""
+    return (f"{f.get('model name', '?')} (family {f.get('cpu family', '?')}, model {f.get('model', '?')}, "
+            f"stepping {f.get('stepping', '?')}, {f.get('cpu MHz', '?')} MHz)")
 
 
 def cpu_baseline(g, w, budget_s: float, threads: int):
