@@ -39,6 +39,9 @@ WORKLOADS = {
     "rmat24_tri_J1024_K50": dict(kind="rmat", scale=24, ef=16, scheme="trivalency", J=1024, K=50, gseed=1,
                                  sseed=1),
 }
+# Ablation: the same RMAT-24 graph without the random vertex relabelling
+# (RMAT's own id order, hubs at ids with many zero bits).
+WORKLOADS["rmat24_p0.01_J1024_K50_unpermuted"] = dict(WORKLOADS["rmat24_p0.01_J1024_K50"], relabel=False)
 # Road-network stand-in (the paper's named weak case: high diameter, few arcs
 # per vertex): 1024 x 1024 lattice of two-way links, 10% removed.
 WORKLOADS["road1024_p0.3_J256_K50"] = dict(kind="road", width=1024, drop=0.1, scheme="0.3", J=256, K=50, gseed=1,
@@ -54,7 +57,7 @@ VARIANTS = {"rmat24_p0.01_J1024_K50": ["rmat24_tri_J1024_K50"]}
 def make_graph(w):
     import graphgen
     if w["kind"] == "rmat":
-        g = graphgen.rmat(w["scale"], w["ef"], seed=w["gseed"])
+        g = graphgen.rmat(w["scale"], w["ef"], seed=w["gseed"], relabel=w.get("relabel", True))
     elif w["kind"] == "road":
         g = graphgen.road_grid(w["width"], w["width"], w["drop"], seed=w["gseed"])
     else:
