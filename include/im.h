@@ -348,9 +348,10 @@ uint64_t im_query_footprint(const im_graph* g, int32_t J, int32_t K);
 void im_engine_free(im_engine* e);
 
 /* G independent queries in one engine, run to completion: seeds_out[i] is an
- * int32[K[i]] host buffer, spread_out (optional) double[G].  The engine runs
- * in graph mode (use_graphs = 1): its steps are captured and replayed, the
- * workgroups of each launch split among the queries on the device. */
+ * int32[K[i]] host buffer, spread_out (optional) double[G].  With 16 or more
+ * queries the engine runs in graph mode (use_graphs = 1): its steps are
+ * captured and replayed; in both modes the workgroups of each launch are split
+ * among the queries on the device. */
 im_status im_select_seeds_batch(int32_t G, const im_graph* const* graphs, const int32_t* J, const uint64_t* seed,
                                 const int32_t* K, int32_t* const* seeds_out, double* spread_out, void* stream);
 

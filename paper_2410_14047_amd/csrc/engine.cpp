@@ -1340,10 +1340,12 @@ im_status im_select_seeds_batch(int32_t G, const im_graph* const* graphs, const 
     if (G < 1 || !graphs || !J || !seed || !K || !seeds_out) return imx::set_error(IM_EINVAL, "NULL argument");
     im_engine* e = nullptr;
     if (im_status st = im_engine_create(G, 0, stream, &e)) return st;
-    // many queries of one call: captured steps with device-side splits (the
-    // launch sequence changes only when a query finishes)
+    // many queries of one call (16 or more): captured steps with device-side
+    // splits (the launch sequence changes only when a query finishes).  Fewer
+    // queries use direct launches: a captured step launches every kernel kind
+    // every round, which few queries cannot fill (one large query: 46% slower).
     im_tuning t = e->eng->tuning();
-    t.use_graphs = 1;
+    t.use_graphs = G >= 16 ? 1 : 0;
     if (im_status st = e->eng->set_tuning(t)) {
         im_engine_free(e);
         return st;
