@@ -229,10 +229,16 @@ def cpu_baseline(g, w, budget_s: float, threads: int):
 
 
 def batched_main(args):
+    print(json.dumps(batched_result(tune=True)), flush=True)
+
+
+def batched_result(tune: bool = True) -> dict:
     """64 independent graphs of uneven size (32 RMAT, scales 12-18; 32
     Barabasi-Albert, n 10k-200k, m0=8), weighted cascade, J=256, K=20, sketch
     seeds 0..63: one engine (batched launches) against one query per launch
-    (sequential one-query engines), with identical outputs required."""
+    (sequential one-query engines), with identical outputs required.  With
+    `tune`, the engine's tuning is autotuned on every 8th query first;
+    otherwise the library's defaults are used."""
     import numpy as np
     import torch
 
@@ -257,11 +263,14 @@ def batched_main(args):
     queries = [(G, J, i, K) for i, G in enumerate(Gs)]
 
     # autotune on every 8th query (not timed)
-    tuned = autotune.autotune(queries[::8], candidates=[
-        dict(group_first=gf, group_rest=gr, rounds_per_step=r, dense_div=16)
-        for gf in (0, 64) for gr in (0, 32, 64) for r in (4, 8, 16)], stream=stream)
-    tuning = tuned["best"]
-    print(f"[bench] tuning {tuning}", file=sys.stderr, flush=True)
+    if tune:
+        tuned = autotune.autotune(queries[::8], candidates=[
+            dict(group_first=gf, group_rest=gr, rounds_per_step=r, dense_div=16)
+            for gf in (0, 64) for gr in (0, 32, 64) for r in (4, 8, 16)], stream=stream)
+        tuning = tuned["best"]
+    else:
+        tuning = {}
+    print(f"[bench] tuning {tuning or 'library defaults'}", file=sys.stderr, flush=True)
 
     counters = {}
 
@@ -299,7 +308,9 @@ def batched_main(args):
             assert list(ra["seeds"]) == list(rb["seeds"]) and list(ra["T"]) == list(rb["T"]), "outputs differ"
     upd = sum(J * G.m * r["stats"]["total_sweeps"] for G, r in zip(Gs, a))
     tb, ts = times["batched"][0], times["one_query_per_launch"][0]
-    print(json.dumps({
+    for G in Gs:
+        G.free()
+    return {
         "metric": "batched IM queries: wall time of 64 queries (and register updates/s)",
         "value": 64 / tb, "unit": "queries/s", "n_gpus": 1, "higher_is_better": True,
         "batched_s": tb, "batched_hip_graphs_s": times["batched_hip_graphs"][0], "one_query_per_launch_s": ts,
@@ -307,7 +318,7 @@ def batched_main(args):
         "register_updates_per_s": upd / tb, "identical_outputs": True, "tuning": tuning,
         "config": {"workload": "batched64_rmat12-18_ba10k-200k_wc_J256_K20", "graphs": 64,
                    "arcs": int(sum(g.m for g in gs)), "J": J, "K": K},
-        "data": "synthetic", "dtype": "u8"}), flush=True)
+        "data": "synthetic", "dtype": "u8"}
 
 
 def served_main(args):
@@ -506,6 +517,8 @@ def main():
     ap.add_argument("--no-tail", action="store_true",
                     help="run every sweep and cascade level on the full grid (no single-workgroup tail kernels); "
                          "the profile that the roofline's mean launch time is checked against uses it")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="default workload only: skip the batched-queries comparison in the line")
     ap.add_argument("--no-variants", action="store_true",
                     help="measure only the named workload (not the variants reported beside it)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work in cpu_baseline")
@@ -610,6 +623,12 @@ def main():
             out["variants"][name]["unit"] = "register updates/s"
             out["variants"][name]["steps"] = max(1, args.steps // 2 + 1)
             del gv
+    if args.workload == DEFAULT and not args.no_batched:
+        # the batched-queries comparison (library default tuning), so the
+        # default line carries it too
+        b = batched_result(tune=False)
+        out["batched"] = {k: b[k] for k in ("value", "unit", "batched_s", "batched_hip_graphs_s",
+                                            "one_query_per_launch_s", "speedup", "identical_outputs", "config")}
     print(json.dumps(out), flush=True)
 
 
