@@ -125,6 +125,18 @@ def test_select_seeds_batch_api(imx):
         assert list(sd) == list(r["seeds"]) and sp == r["spread"]
 
 
+def test_select_seeds_batch_api_graph_mode(imx):
+    """From 16 queries up the batch call captures its steps and replays them;
+    every result equals the query run alone."""
+    g = graphgen.with_p(graphgen.erdos_renyi(400, 2000, 7), "0.2")
+    G = imx.Graph.from_graphgen(g)
+    n = 18
+    seeds, spread = imx.im_select_seeds_batch([G] * n, [64] * n, list(range(n)), [3 + s % 4 for s in range(n)])
+    for s in range(n):
+        r = _solo(imx, G, 64, s, 3 + s % 4)
+        assert list(seeds[s]) == list(r["seeds"]) and spread[s] == r["spread"]
+
+
 def test_engine_many_queries_one_graph(imx):
     """More queries than one launch holds (64) on one graph, different seeds."""
     g = graphgen.with_p(graphgen.erdos_renyi(400, 2000, 5), "0.2")
@@ -154,14 +166,23 @@ def test_server_results_equal_solo(imx, orc):
     solo = [_solo(imx, graphs[gname], J, seed, K) for (ta, gname, J, seed, K) in trace]
     for (ta, gname, J, seed, K), r in zip(trace, solo):
         _same_as_oracle(r, orc.greedy(host[gname], J, seed, K, keep_registers=False))
-    for lanes in (None, [256 << 10]):  # one engine; two engines on their own streams
-        srv = serve.Server(graphs, max_queries=6, lanes=lanes).start()
+    # one engine; two engines on their own streams; two engines with classes
+    # seen to finish quickly routed to the first lane whatever their footprint
+    for lanes, quick in ((None, 0.0), ([256 << 10], 0.0), ([256 << 10], 60.0)):
+        srv = serve.Server(graphs, max_queries=6, lanes=lanes, quick_s=quick).start()
+        if quick:  # one query of every class first, so the server has seen each finish
+            for gname, J in sorted({(gname, J) for (ta, gname, J, seed, K) in trace}):
+                srv.submit(gname, J, 1000, 2).result()
         res, makespan = serve.replay(srv, trace)
         srv.stop()
         summ = serve.latency_summary(res, makespan)
-        _say(f"[serve] lanes={lanes} {summ}")
-        if lanes:
+        _say(f"[serve] lanes={lanes} quick_s={quick} {summ}")
+        if lanes and not quick:
             assert {r["lane"] for r in res} == {0, 1}
+        if quick:
+            big = [r for (ta, gname, J, seed, K), r in zip(trace, res)
+                   if imx.im_query_footprint(graphs[gname].handle, J, K) > lanes[0]]
+            assert big and all(r["lane"] == 0 for r in big)  # large-footprint queries rerouted
         for r, s in zip(res, solo):
             _same(r, s)
 
