@@ -348,16 +348,11 @@ def served_main(args):
     scales = [int(x) for x in args.served_scales.split(",")]
     graphs = {}
     t0 = time.perf_counter()
-    for i, sc in enumerate(scales):
-        base = graphgen.rmat(sc, 16, seed=1 if i < len(scales) - 1 or scales.count(sc) == 1 else 2)
-        for scheme in ("0.01", "wc"):
-            graphs[f"rmat{sc}_{i}_{scheme}"] = imx.Graph.from_graphgen(graphgen.with_p(base, scheme), stream=stream)
+    for name in graphgen.served_graph_names(scales):
+        graphs[name] = imx.Graph.from_graphgen(graphgen.served_graph(name, scales), stream=stream)
     print(f"[bench] {len(graphs)} resident graphs ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
-    names = sorted(graphs)
-    rng = np.random.Generator(np.random.PCG64(1))
     nq = args.served_queries
-    reqs = [(names[int(rng.integers(len(names)))], int(rng.choice([128, 512])), int(i),
-             int(rng.integers(10, 101))) for i in range(nq)]
+    reqs = graphgen.served_requests(nq, scales)
 
     if args.served_service_in:
         sv = json.load(open(args.served_service_in))

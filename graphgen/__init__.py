@@ -22,7 +22,7 @@ import numpy as np
 __all__ = [
     "Graph", "csr_from_edges", "erdos_renyi", "rmat", "barabasi_albert", "road_grid",
     "uniform_p", "weighted_cascade_p", "trivalency_p", "with_p",
-    "save_npz", "load_npz", "cached",
+    "save_npz", "load_npz", "cached", "SERVED_SCALES", "served_graph_names", "served_graph", "served_requests",
 ]
 
 
@@ -256,3 +256,37 @@ def cached(path: Optional[str], make) -> Graph:
         os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
         save_npz(g, path)
     return g
+
+
+# ---------------------------------------------------------------------------
+# Served-queries workload: resident RMAT graphs (edge factor 16) at these
+# scales, the last with another generator seed, each under p = 0.01 and
+# weighted cascade; a request stream over them.
+
+SERVED_SCALES = (16, 17, 18, 19, 20, 21, 22, 22)
+
+
+def served_graph_names(scales=SERVED_SCALES):
+    """Graph names of the served workload, sorted: rmat<scale>_<index>_<scheme>."""
+    return sorted(f"rmat{sc}_{i}_{scheme}" for i, sc in enumerate(scales) for scheme in ("0.01", "wc"))
+
+
+def served_graph(name: str, scales=SERVED_SCALES) -> Graph:
+    """The graph of a served-workload name (generated; seed 1, or 2 for a
+    repeated scale's later copy)."""
+    _, idx, scheme = name.split("_")
+    i = int(idx)
+    sc = scales[i]
+    seed = 1 if i < len(scales) - 1 or list(scales).count(sc) == 1 else 2
+    return with_p(rmat(sc, 16, seed=seed), scheme)
+
+
+def served_requests(count: int, scales=SERVED_SCALES, seed: int = 1):
+    """The served workload's request stream: (graph name, J, sketch seed, K)
+    with the graph uniform over the names, J uniform over {128, 512}, K
+    uniform in [10, 100] and the sketch seed = the request's index."""
+    names = served_graph_names(scales)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return [(names[int(rng.integers(len(names)))], int(rng.choice([128, 512])), int(i), int(rng.integers(10, 101)))
+            for i in range(count)]
+

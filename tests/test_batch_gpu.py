@@ -292,3 +292,34 @@ def test_engine_grid_cap_and_tail_modes(imx):
         for qid, r in zip(ids, solo):
             _same(res[qid], r)
         E.free()
+
+
+def test_served_workload_sample_matches_oracle(imx):
+    """A sample of the served-queries workload itself (eight requests of its
+    stream on the scale-16 and scale-17 RMAT graphs, both probability schemes,
+    K up to 98), served together through the benchmark's lane policy: every
+    result equals the oracle's, stored by tests/golden/make_served_sample.py
+    (the oracle takes about 20 minutes for these, too long for this run)."""
+    import json
+    import os
+    from paper_2410_14047_amd import serve
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "served_sample.json")))
+    assert gold["scales"] == list(graphgen.SERVED_SCALES)
+    qs = gold["queries"]
+    assert qs and [(q["graph"], q["J"], q["seed"], q["K"]) for q in qs] == [
+        r for r in graphgen.served_requests(gold["stream"])
+        if r[0].startswith(("rmat16_", "rmat17_")) and not (r[1] == 512 and r[0].endswith("_wc"))][:len(qs)]
+    graphs = {name: imx.Graph.from_graphgen(graphgen.served_graph(name)) for name in sorted({q["graph"] for q in qs})}
+    srv = serve.Server(graphs, max_queries=[16, 1], lanes=[128 << 20], quick_s=0.1).start()
+    futs = [srv.submit(q["graph"], q["J"], q["seed"], q["K"]) for q in qs]
+    res = [f.result(timeout=240) for f in futs]
+    srv.stop()
+    for q, r in zip(qs, res):
+        _say(f"[served sample] {q['graph']} J={q['J']} seed={q['seed']} K={q['K']} lane {r['lane']}")
+        assert [int(x) for x in r["seeds"]] == q["seeds"], q["graph"]
+        assert [int(x) for x in r["T"]] == q["T"]
+        assert [float(x).hex() for x in r["est"]] == q["est_hex"]
+        assert float(r["spread"]).hex() == q["spread_hex"]
+        assert r["stats"]["rebuilds"] == q["rebuilds"]
+    for G in graphs.values():
+        G.free()
