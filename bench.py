@@ -239,21 +239,14 @@ def batched_result(tune: bool = True) -> dict:
     (sequential one-query engines), with identical outputs required.  With
     `tune`, the engine's tuning is autotuned on every 8th query first;
     otherwise the library's defaults are used."""
-    import numpy as np
     import torch
 
     import graphgen
     import paper_2410_14047_amd as imx
     from paper_2410_14047_amd import autotune
 
-    rng = np.random.Generator(np.random.PCG64(4))
-    specs = [("rmat", int(rng.integers(12, 19)), i) for i in range(32)]
-    specs += [("ba", int(rng.integers(10_000, 200_001)), i) for i in range(32)]
     t0 = time.perf_counter()
-    gs = []
-    for kind, size, i in specs:
-        g = graphgen.rmat(size, 16, seed=100 + i) if kind == "rmat" else graphgen.barabasi_albert(size, 8, seed=i)
-        gs.append(graphgen.with_p(g, "wc"))
+    gs = [graphgen.batched_graph(spec) for spec in graphgen.batched_specs()]
     print(f"[bench] 64 graphs, {sum(g.m for g in gs)} arcs ({time.perf_counter() - t0:.1f} s)", file=sys.stderr,
           flush=True)
     torch.cuda.set_device(0)

@@ -23,6 +23,7 @@ __all__ = [
     "Graph", "csr_from_edges", "erdos_renyi", "rmat", "barabasi_albert", "road_grid",
     "uniform_p", "weighted_cascade_p", "trivalency_p", "with_p",
     "save_npz", "load_npz", "cached", "SERVED_SCALES", "served_graph_names", "served_graph", "served_requests",
+    "batched_specs", "batched_graph",
 ]
 
 
@@ -289,4 +290,23 @@ def served_requests(count: int, scales=SERVED_SCALES, seed: int = 1):
     rng = np.random.Generator(np.random.PCG64(seed))
     return [(names[int(rng.integers(len(names)))], int(rng.choice([128, 512])), int(i), int(rng.integers(10, 101)))
             for i in range(count)]
+
+
+# ---------------------------------------------------------------------------
+# Batched-queries workload: 64 graphs of uneven size, weighted cascade.
+
+def batched_specs():
+    """(kind, size, index) of the 64 graphs: 32 RMAT with scales uniform in
+    12..18, then 32 Barabasi-Albert with n uniform in 10k..200k (m0 = 8)."""
+    rng = np.random.Generator(np.random.PCG64(4))
+    specs = [("rmat", int(rng.integers(12, 19)), i) for i in range(32)]
+    specs += [("ba", int(rng.integers(10_000, 200_001)), i) for i in range(32)]
+    return specs
+
+
+def batched_graph(spec) -> Graph:
+    """The weighted-cascade graph of one batched-workload spec."""
+    kind, size, i = spec
+    g = rmat(size, 16, seed=100 + i) if kind == "rmat" else barabasi_albert(size, 8, seed=i)
+    return with_p(g, "wc")
 

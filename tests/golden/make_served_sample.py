@@ -8,7 +8,7 @@ scale-16 and scale-17 graphs, leaving out those with J = 512 on a
 weighted-cascade graph (their oracle runs take hours).  Only `graphgen` (the
 inputs) and `oracle` are used.
 
-    python tests/golden/make_served_sample.py     (about 20 minutes, 8 processes)
+    python tests/golden/make_served_sample.py     (about 10 minutes, 8 processes)
 """
 import json
 import multiprocessing

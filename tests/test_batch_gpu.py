@@ -299,7 +299,7 @@ def test_served_workload_sample_matches_oracle(imx):
     stream on the scale-16 and scale-17 RMAT graphs, both probability schemes,
     K up to 98), served together through the benchmark's lane policy: every
     result equals the oracle's, stored by tests/golden/make_served_sample.py
-    (the oracle takes about 20 minutes for these, too long for this run)."""
+    (the oracle takes about 10 minutes for these, too long for this run)."""
     import json
     import os
     from paper_2410_14047_amd import serve
@@ -322,4 +322,39 @@ def test_served_workload_sample_matches_oracle(imx):
         assert float(r["spread"]).hex() == q["spread_hex"]
         assert r["stats"]["rebuilds"] == q["rebuilds"]
     for G in graphs.values():
+        G.free()
+
+
+def test_batched_workload_sample_matches_oracle(imx):
+    """The batched-queries workload itself (64 weighted-cascade graphs of
+    uneven size, J = 256, K = 20) in one engine, directly and in graph mode:
+    the two runs agree on every query, and the sampled queries (the eight
+    smallest graphs and the smallest Barabasi-Albert one) equal the oracle's
+    results stored by tests/golden/make_batched_sample.py."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "batched_sample.json")))
+    specs = graphgen.batched_specs()
+    Gs = [imx.Graph.from_graphgen(graphgen.batched_graph(sp)) for sp in specs]
+    runs = []
+    for graphs in (0, 1):
+        E = imx.Engine(max_queries=64)
+        E.set_tuning(use_graphs=graphs)
+        ids = [E.submit(G, 256, q, 20) for q, G in enumerate(Gs)]
+        res = E.run()
+        _say(f"[batched workload] use_graphs={graphs} {E.counters()}")
+        E.free()
+        runs.append([res[i] for i in ids])
+    for a, b in zip(*runs):
+        _same(a, b)
+    for g in gold["queries"]:
+        q = g["query"]
+        assert list(specs[q]) == g["spec"] and g["J"] == 256 and g["K"] == 20 and g["seed"] == q
+        r = runs[0][q]
+        assert [int(x) for x in r["seeds"]] == g["seeds"], q
+        assert [int(x) for x in r["T"]] == g["T"]
+        assert [float(x).hex() for x in r["est"]] == g["est_hex"]
+        assert float(r["spread"]).hex() == g["spread_hex"]
+        assert r["stats"]["rebuilds"] == g["rebuilds"]
+    for G in Gs:
         G.free()
