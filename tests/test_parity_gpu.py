@@ -83,6 +83,10 @@ CASES = {
     "er400_normal_J128": (lambda: graphgen.with_p(graphgen.erdos_renyi(400, 4000, 9), "normal"), 128, 16, 8),
     "rmat11_uniform01_J256": (lambda: graphgen.with_p(graphgen.rmat(11, 16, seed=4), "uniform01"), 256, 17, 6),
     "rmat11_p0.005_J1024": (lambda: graphgen.with_p(graphgen.rmat(11, 16, seed=6), "0.005"), 1024, 18, 6),
+    # road-network stand-ins (lattice, 10% of links removed): high diameter,
+    # degree <= 4, so the tail kernels run by default
+    "road48_p0.6_J256": (lambda: graphgen.with_p(graphgen.road_grid(48, 48, 0.1, seed=3), "0.6"), 256, 20, 8),
+    "road64_p0.3_J64": (lambda: graphgen.with_p(graphgen.road_grid(64, 64, 0.1, seed=3), "0.3"), 64, 20, 10),
 }
 
 
@@ -128,7 +132,8 @@ TAIL_SETTINGS = {
 TAIL_CASES = dict(CASES)
 TAIL_CASES["er6000_p0.5_J64"] = (lambda: graphgen.with_p(graphgen.erdos_renyi(6000, 60000, 11), "0.5"), 64, 19, 4)
 TAIL_CASE_NAMES = ["c1_er1k_p0.1_J64_s1", "er400_wc_J128", "er300_tri_J192", "er150_p0.3_J4096", "hub2000_p0.2_J256",
-                   "rmat12_wc_J512", "ba3000_wc_J256", "cycle50_p1_J64", "er60_p1_J128_Kn", "er6000_p0.5_J64"]
+                   "rmat12_wc_J512", "ba3000_wc_J256", "cycle50_p1_J64", "er60_p1_J128_Kn", "er6000_p0.5_J64",
+                   "road48_p0.6_J256"]
 
 
 @pytest.mark.parametrize("setting", list(TAIL_SETTINGS))
