@@ -75,3 +75,32 @@ def test_bench_monte_carlo_evaluator():
                           p=np.full(2, 0.5, np.float32))
     s = bench.mc_spread(path, [0], 4000, rng)
     assert abs(s.mean() - 1.75) < 0.06
+
+
+def test_served_and_batched_workload_recipes():
+    """The served and batched workloads' inputs: 16 resident graph names, a
+    request stream with J in {128, 512}, K in [10, 100] and the sketch seed
+    equal to the index, uniform over the graphs; 64 batched specs (32 RMAT of
+    scales 12..18, then 32 BA of 10k..200k vertices); all deterministic."""
+    import collections
+    names = graphgen.served_graph_names()
+    assert len(names) == 16 and names == sorted(names)
+    assert {n.split("_")[2] for n in names} == {"0.01", "wc"}
+    reqs = graphgen.served_requests(1000)
+    assert reqs == graphgen.served_requests(1000) and reqs[:10] == graphgen.served_requests(10)
+    assert [r[2] for r in reqs] == list(range(1000))
+    assert {r[1] for r in reqs} == {128, 512} and all(10 <= r[3] <= 100 for r in reqs)
+    counts = collections.Counter(r[0] for r in reqs)
+    assert set(counts) == set(names) and min(counts.values()) > 30  # ~62 each
+    g = graphgen.served_graph("rmat16_0_wc")
+    assert g.n == 1 << 16 and g.p is not None
+    # the repeated scale's second copy uses another generator seed
+    assert graphgen.served_graph_names().count("rmat22_6_wc") == 1 and "rmat22_7_wc" in names
+    specs = graphgen.batched_specs()
+    assert len(specs) == 64 and specs == graphgen.batched_specs()
+    assert all(k == "rmat" and 12 <= s <= 18 for k, s, _ in specs[:32])
+    assert all(k == "ba" and 10_000 <= s <= 200_000 for k, s, _ in specs[32:])
+    assert [i for _, _, i in specs] == list(range(32)) * 2
+    small = min(specs[:32], key=lambda sp: sp[1])
+    gb = graphgen.batched_graph(small)
+    assert gb.n == 1 << small[1] and np.all(gb.p > 0)
