@@ -537,13 +537,6 @@ im_status Engine::step()
     const int gs_first_ = tune_.group_first, gs_rest_ = tune_.group_rest;
     args_off_ = 0;
 
-    // Chunks of at most kMaxBatch queries per launch.
-    auto chunks = [](const std::vector<Query*>& v) {
-        std::vector<std::vector<Query*>> out;
-        for (size_t i = 0; i < v.size(); i += kMaxBatch)
-            out.emplace_back(v.begin() + i, v.begin() + std::min(v.size(), i + kMaxBatch));
-        return out;
-    };
     const bool stats = profiling_level() >= 2;
     // Small frontiers go to the tail kernels (not in instrumented runs, whose
     // counters cover the full-grid propagation kernel only).
@@ -591,6 +584,7 @@ im_status Engine::step()
         }
         return out;
     };
+    // chunks of at most kMaxBatch records per launch
     auto mchunks = [](const std::vector<Member>& v) {
         std::vector<std::vector<Member>> out;
         for (size_t i = 0; i < v.size(); i += kMaxBatch)
