@@ -290,7 +290,10 @@ im_status im_engine_create(int32_t max_queries, uint64_t hbm_budget_bytes, void*
  *                            sequence changes only when a query is admitted
  *                            or finishes; it is captured in a HIP graph the
  *                            first time it occurs and replayed while it
- *                            repeats (no per-launch kernel times then);
+ *                            repeats (no per-launch kernel times then); it
+ *                            pays only when many queries share the engine
+ *                            (with one large query the empty launches cost
+ *                            more than the capture saves);
  *                            0: direct launches of the queries in each stage;
  *   grid_cap                 at most this many workgroups in any launch of
  *                            the engine (0: no cap), e.g. to keep an engine of
@@ -304,7 +307,11 @@ im_status im_engine_create(int32_t max_queries, uint64_t hbm_budget_bytes, void*
  * IMX_GROUP, IMX_ROUNDS, IMX_DENSE_DIV, IMX_GRAPHS and IMX_TAIL override them at
  * engine creation (an out-of-range value makes creation fail with IM_EINVAL).
  * IMX_PROP_GRID (>= 1), read at engine creation, caps the workgroups of a
- * propagation launch (a test of schedule independence; never faster). */
+ * propagation launch (a test of schedule independence; never faster).
+ * A launch that carries several queries (and every launch in graph mode)
+ * divides its workgroups among them on the device, by each query's current
+ * work; IMX_DYN_SPLIT=0 at engine creation divides them on the host by graph
+ * size instead. */
 typedef struct im_tuning {
     int32_t group_first;
     int32_t group_rest;
