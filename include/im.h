@@ -291,9 +291,8 @@ im_status im_engine_create(int32_t max_queries, uint64_t hbm_budget_bytes, void*
  *                            or finishes; it is captured in a HIP graph the
  *                            first time it occurs and replayed while it
  *                            repeats (no per-launch kernel times then); it
- *                            pays only when many queries share the engine
- *                            (with one large query the empty launches cost
- *                            more than the capture saves);
+ *                            is meant for many queries in one engine (with
+ *                            one large query it was measured 46% slower);
  *                            0: direct launches of the queries in each stage;
  *   grid_cap                 at most this many workgroups in any launch of
  *                            the engine (0: no cap), e.g. to keep an engine of
