@@ -314,6 +314,17 @@ def batched_result(tune: bool = True) -> dict:
         "data": "synthetic", "dtype": "u8"}
 
 
+def fifo_latencies(arrivals, service):
+    """Time in system of each request at one first-come-first-served server
+    that is never idle while requests wait: request i starts at the later of
+    its arrival and the previous finish.  Returns (latencies, last finish)."""
+    fin, lat = 0.0, []
+    for ta, st in zip(arrivals, service):
+        fin = max(fin, float(ta)) + float(st)
+        lat.append(fin - float(ta))
+    return lat, fin
+
+
 def served_main(args):
     """Poisson stream of IM queries over device-resident graphs (RMAT scales
     given by --served-scales, edge factor 16, two p-schemes each), J in
@@ -387,10 +398,7 @@ def served_main(args):
         arr = np.cumsum(np.random.Generator(np.random.PCG64(int(round(load * 1000)))).exponential(1.0 / lam, size=nq))
         trace = [(float(t), *r) for t, r in zip(arr, reqs)]
         # serial: FIFO single server on the measured service times
-        fin, lat = 0.0, []
-        for ta, st in zip(arr, service):
-            fin = max(fin, ta) + st
-            lat.append(fin - ta)
+        lat, fin = fifo_latencies(arr, service)
         lat = np.array(lat) * 1e3
         row = {"load": load, "lambda_qps": lam,
                "serial": {"queries": nq, "throughput_qps": nq / fin, "p50_ms": float(np.percentile(lat, 50)),
