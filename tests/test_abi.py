@@ -127,3 +127,39 @@ def test_allocator_hooks_outlive_reinstallation(imx):
     fptr = ctypes.cast(first[1], ctypes.c_void_p).value
     ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)(fptr)(ctypes.c_void_p(0x1234), None)
     assert freed == [0x1234]
+
+
+def test_plain_c_program_compiles_links_and_runs(imx, tmp_path):
+    """The header is plain C (C99, pedantic) and a C program links against
+    libimx.so and calls it: version, and a malformed graph rejected with
+    IM_EINVAL and a message (no device needed)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    src = tmp_path / "use_im.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include "im.h"
+int main(void)
+{
+    int32_t major = 0, minor = 0;
+    if (im_version(&major, &minor) != IM_OK || (major == 0 && minor < 1)) return 1;
+    const int64_t rowptr[3] = {0, 1, 3};          /* rowptr[n] != m */
+    const int32_t col[2] = {1, 0};
+    const float p[2] = {0.5f, 0.5f};
+    im_graph* g = NULL;
+    if (im_graph_load(2, 2, rowptr, col, p, NULL, &g) != IM_EINVAL || g != NULL) return 2;
+    const char* msg = im_last_error();
+    if (!msg || !msg[0]) return 3;
+    printf("%d.%d %s\n", major, minor, msg);
+    return 0;
+}
+''')
+    lib_dir = os.path.dirname(imx.binding.LIB_PATH)
+    exe = tmp_path / "use_im"
+    subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I",
+                           os.path.join(ROOT, "include"), str(src), "-L", lib_dir, "-limx",
+                           f"-Wl,-rpath,{lib_dir}", "-o", str(exe)])
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, (out.returncode, out.stdout, out.stderr)
